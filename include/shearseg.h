@@ -1,0 +1,169 @@
+/*
+ * shearseg.h - C ABI of the MI355X (gfx950) library for shearlet-regularised convex
+ * multi-label image segmentation (Haeuser & Steidl, "Convex Multiclass Segmentation
+ * with Shearlet Regularization", arXiv 1112.1805).
+ *
+ * The library computes, on one GPU, the ADMM iteration of Section 3 for the model
+ *
+ *     min_u  <u, s> + || Lambda (I_q (x) S) u ||_1 + iota_C(u)     (problemSegmentation)
+ *
+ * where S is the FFT-based, translation-invariant discrete shearlet transform of
+ * Section 2 (a Parseval frame, S^T S = I), s the data term of eq. (computationOfs) and
+ * C the per-pixel probability simplex.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every call returns shs_status (0 = SHS_OK, < 0 = error); nothing throws across the ABI.
+ *   shs_last_error() returns a thread-local message for the last failing call.
+ * - d_* pointers are caller-owned DEVICE memory on the plan's device, contiguous and
+ *   row-major; h_* pointers are caller-owned HOST memory.  The library never frees or
+ *   retains caller memory beyond the call.
+ * - Images are square N x N arrays indexed [y][x]; axis 0 carries the frequency omega_1 of
+ *   the paper (the paper vectorises column-wise: a layout choice only).  Label-indexed
+ *   arrays are label-major ([q][N][N], the "q layers" of Section 3).
+ * - `stream` is a hipStream_t (NULL = the legacy default stream).  All work is enqueued
+ *   asynchronously on it; only calls that return host results (h_stats, h_energy)
+ *   synchronise that stream before returning.
+ * - Inputs are never written.  Outputs are defined only when the call returns SHS_OK.
+ * - Filter order (used by d_c and d_psi layouts and by per-filter weights):
+ *     0 = low-pass; then for each scale j = 0..J-1: the horizontal-cone shears
+ *     k = -(2^j-1)..(2^j-1), the vertical-cone shears in the same order, then the two
+ *     glued seam filters k = -2^j and k = +2^j.  eta = 1 + 4 (2^J - 1) filters
+ *     (5, 13, 29, 61 for J = 1..4; Theorem 2.2's system, Remark 2.3's "61 images").
+ * - Frequency scaling: filters are evaluated at xi = (4^J / N) * omega (omega the integer
+ *   frequency of Section 2), which is the paper's integer grid when N = 4^J and keeps the
+ *   J-scale radial partition exact up to the Nyquist frequency otherwise.  For even N the
+ *   Nyquist bins hold sqrt((psi(w)^2 + psi(-w)^2)/2), which keeps sum_j psi_j^2 = 1 and
+ *   the coefficients real.
+ */
+#ifndef SHEARSEG_H
+#define SHEARSEG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SHS_OK = 0,
+  SHS_E_INVALID = -1,      /* bad argument (null pointer, size, parameter out of range) */
+  SHS_E_UNSUPPORTED = -2,  /* valid per the paper but not implemented (e.g. image size) */
+  SHS_E_NOMEM = -3,        /* device allocation for plan constants failed */
+  SHS_E_DEVICE = -4,       /* a HIP runtime call or kernel launch failed */
+  SHS_E_NUMERIC = -5,      /* NaN/Inf met in the FP64 residual reduction */
+  SHS_E_WORKSPACE = -6     /* workspace missing or smaller than shs_workspace_bytes() */
+} shs_status;
+
+/* Storage type of the dominant ADMM state (the eta*q coefficient images); arithmetic is
+ * FP32 throughout, residual and energy reductions FP64. */
+typedef enum { SHS_STORE_F32 = 0, SHS_STORE_BF16 = 1, SHS_STORE_F16 = 2 } shs_store;
+
+#define SHS_MAX_LABELS 8
+#define SHS_MAX_CHANNELS 4
+
+typedef struct shs_plan shs_plan;   /* opaque: filter bank, twiddles, sizes, device */
+
+typedef struct {
+  int32_t n;         /* image side N (square images, Section 2); 64..2048, power of two */
+  int32_t channels;  /* 1 = gray, 3 = RGB (data term only); 1..SHS_MAX_CHANNELS */
+  int32_t q;         /* number of labels, 1..SHS_MAX_LABELS */
+  int32_t J;         /* number of shearlet scales, J >= 1 and 4^J <= 2N */
+  int32_t store;     /* shs_store */
+} shs_shape;
+
+typedef struct {
+  const float* lambda;  /* HOST array: J+1 weights Lambda = (lambda_0 low-pass, lambda_1..lambda_J
+                           per scale) as in Section 3, or eta per-filter weights; all >= 0 */
+  int32_t lambda_len;   /* J+1 or eta */
+  float gamma;          /* ADMM penalty gamma > 0 (Section 3, general ADMM) */
+  int32_t iters;        /* maximum number of ADMM iterations, >= 0 */
+  double tol;           /* 0: run exactly `iters`; > 0: stop after the first checked iteration
+                           whose combined residual sqrt(|dy|^2 + |db|^2) <= tol * sqrt(q N^2) */
+  int32_t check_every;  /* residual check period when tol > 0 (>= 1) */
+  int32_t resume;       /* 0: start from v = w = b = 0; 1: continue from the state left in the
+                           workspace by a previous shs_solve on the same plan and workspace */
+} shs_params;
+
+typedef struct {
+  int32_t iters_done;
+  double energy;            /* F(u*) = <u*, s> + sum_l sum_j lambda_j ||S_j u*_l||_1, exact (FP64 sum) */
+  double energy_surrogate;  /* <w, s> + sum lambda_j |v| of the last iterate (free by-product) */
+  double r_primal;          /* ||b^K - b^(K-1)||                 (b = (b_v, b_w)) */
+  double r_dual;            /* ||y^K - y^(K-1)|| / gamma           (y = (v, w))     */
+  double r_combined;        /* ||y^K - y^(K-1)||^2 + ||b^K - b^(K-1)||^2            */
+} shs_stats;
+
+/* ---- plan ------------------------------------------------------------------------
+ * shs_plan_create validates the shape, selects `device` (HIP ordinal), allocates the plan's
+ * constants in device memory (the eta filter spectra and FFT twiddles) and fills them on
+ * the device.  Errors: SHS_E_INVALID (null, q/channels/J out of range),
+ * SHS_E_UNSUPPORTED (N not a supported size), SHS_E_NOMEM, SHS_E_DEVICE.
+ * The plan is immutable after creation and may be shared by concurrent calls that use
+ * distinct workspaces. */
+shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out);
+shs_status shs_plan_destroy(shs_plan* plan);
+
+/* Bytes of device workspace every compute call on this plan needs (0 for a null plan).
+ * The workspace starts with the ADMM state (shs_state_bytes bytes): copying that prefix
+ * out and back is a checkpoint of a solve (see shs_params.resume). */
+size_t shs_workspace_bytes(const shs_plan* plan);
+size_t shs_state_bytes(const shs_plan* plan);
+
+/* eta = 1 + 4 (2^J - 1) (Theorem 2.2's system); -1 for J < 1. */
+int32_t shs_num_filters(int32_t J);
+
+/* Copy the plan's filter bank to d_psi, float32 [eta][N][N/2+1]: filter j at the FFT bins
+ * (k0, k1), k1 <= N/2 (the other half follows from psi(-w) = psi(w)). */
+shs_status shs_filters(const shs_plan* plan, float* d_psi, void* stream);
+
+/* Data term of eq. (computationOfs), colour form of Section 4:
+ * s[k][y][x] = sum_c |f[c][y][x] - codebook[k][c]|^p.
+ * d_img: float32 [channels][N][N]; h_codebook: HOST float32 [q][channels]; p > 0;
+ * d_s: float32 [q][N][N]. */
+shs_status shs_datacost(const shs_plan* plan, const float* d_img, const float* h_codebook, float p,
+                        float* d_s, void* stream);
+
+/* Discrete shearlet transform S (Section 2, eq. (wichtig)) of `count` images (1..q):
+ * d_f float32 [count][N][N]  ->  d_c float32 [count][eta][N][N],
+ * c_j = ifft2(psi_j * fft2(f)).  Uses the workspace. */
+shs_status shs_shearlet_forward(const shs_plan* plan, int32_t count, const float* d_f, float* d_c,
+                                void* d_ws, size_t ws_bytes, void* stream);
+
+/* Adjoint (= inverse, by the Parseval property) transform S^T (Section 2, inverse
+ * paragraph): d_c float32 [count][eta][N][N]  ->  d_f float32 [count][N][N],
+ * f = ifft2(sum_j psi_j * fft2(c_j)). */
+shs_status shs_shearlet_adjoint(const shs_plan* plan, int32_t count, const float* d_c, float* d_f,
+                                void* d_ws, size_t ws_bytes, void* stream);
+
+/* ADMM for (problemSegmentationADMM) (Section 3): starting from v = w = b = 0 (or the
+ * workspace state if params->resume), run params->iters iterations of
+ *   u = 1/2 [ S^T (v - b_v) + (w - b_w) - gamma s ]
+ *   v = shrink_{gamma Lambda}(b_v + S u),  w = P_C(b_w + u),
+ *   b_v += S u - v,  b_w += u - w
+ * (S applied per label).  d_s: float32 [q][N][N] data term.
+ * Outputs: d_u float32 [q][N][N] = w^K (the relaxed labelling, in C); d_labels int32 [N][N]
+ * = index of the largest entry of w^K per pixel, lowest index on ties, 0-based (either may
+ * be NULL).  d_hist: NULL or float64 [iters][4] = (r_primal, r_dual, r_combined,
+ * energy_surrogate) per iteration.  h_stats: NULL (no synchronisation) or receives the final
+ * statistics, including the exact energy (one extra forward transform of w^K).
+ * Errors: SHS_E_INVALID, SHS_E_WORKSPACE, SHS_E_DEVICE, SHS_E_NUMERIC (non-finite residual
+ * at a checked iteration). */
+shs_status shs_solve(const shs_plan* plan, const shs_params* params, const float* d_s, void* d_ws,
+                     size_t ws_bytes, float* d_u, int32_t* d_labels, double* d_hist, shs_stats* h_stats,
+                     void* stream);
+
+/* Energy F(u) = <u, s> + sum_l sum_j lambda_j ||S_j u_l||_1 of (problemSegmentation) for a
+ * given u (float32 [q][N][N]; the indicator term is not evaluated).  Uses params->lambda /
+ * lambda_len only.  Synchronises the stream; result in *h_energy (FP64 accumulation). */
+shs_status shs_energy(const shs_plan* plan, const shs_params* params, const float* d_s, const float* d_u,
+                      void* d_ws, size_t ws_bytes, double* h_energy, void* stream);
+
+const char* shs_status_str(shs_status status);
+const char* shs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHEARSEG_H */

@@ -1,0 +1,238 @@
+"""Python binding of the MI355X shearlet-segmentation library (libshearseg.so).
+
+Argument marshalling only: every function forwards to the C entry point of the same
+name declared in include/shearseg.h.  Device arrays are torch tensors on the plan's GPU
+(their data_ptr() is passed); the stream is torch's current stream.  No computation of
+the method happens in Python, and there is no CPU fallback: if the HIP library is not
+built, importing the binding's functions raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libshearseg.so")
+
+SHS_OK, SHS_E_INVALID, SHS_E_UNSUPPORTED, SHS_E_NOMEM, SHS_E_DEVICE, SHS_E_NUMERIC, SHS_E_WORKSPACE = \
+    0, -1, -2, -3, -4, -5, -6
+SHS_STORE_F32, SHS_STORE_BF16, SHS_STORE_F16 = 0, 1, 2
+STORE_CODES = {"f32": SHS_STORE_F32, "bf16": SHS_STORE_BF16, "f16": SHS_STORE_F16}
+
+
+class ShsShape(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("channels", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("J", ctypes.c_int32), ("store", ctypes.c_int32)]
+
+
+class ShsParams(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.POINTER(ctypes.c_float)), ("lambda_len", ctypes.c_int32),
+                ("gamma", ctypes.c_float), ("iters", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("check_every", ctypes.c_int32), ("resume", ctypes.c_int32)]
+
+
+class ShsStats(ctypes.Structure):
+    _fields_ = [("iters_done", ctypes.c_int32), ("energy", ctypes.c_double),
+                ("energy_surrogate", ctypes.c_double), ("r_primal", ctypes.c_double),
+                ("r_dual", ctypes.c_double), ("r_combined", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ShsError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+_lib = None
+_VP, _SZ, _I32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
+_SIGS = {
+    "shs_plan_create": (_I32, [ctypes.POINTER(ShsShape), ctypes.c_int, ctypes.POINTER(_VP)]),
+    "shs_plan_destroy": (_I32, [_VP]),
+    "shs_workspace_bytes": (_SZ, [_VP]),
+    "shs_state_bytes": (_SZ, [_VP]),
+    "shs_num_filters": (_I32, [_I32]),
+    "shs_filters": (_I32, [_VP, _VP, _VP]),
+    "shs_datacost": (_I32, [_VP, _VP, ctypes.POINTER(ctypes.c_float), ctypes.c_float, _VP, _VP]),
+    "shs_shearlet_forward": (_I32, [_VP, _I32, _VP, _VP, _VP, _SZ, _VP]),
+    "shs_shearlet_adjoint": (_I32, [_VP, _I32, _VP, _VP, _VP, _SZ, _VP]),
+    "shs_solve": (_I32, [_VP, ctypes.POINTER(ShsParams), _VP, _VP, _SZ, _VP, _VP, _VP,
+                         ctypes.POINTER(ShsStats), _VP]),
+    "shs_energy": (_I32, [_VP, ctypes.POINTER(ShsParams), _VP, _VP, _VP, _SZ,
+                          ctypes.POINTER(ctypes.c_double), _VP]),
+    "shs_status_str": (ctypes.c_char_p, [_I32]),
+    "shs_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Load libshearseg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1112_1805_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != SHS_OK:
+        raise ShsError(status, where, lib().shs_last_error().decode())
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _expect(t, shape, dtype_name, what):
+    import torch
+    dt = {"f32": torch.float32, "f64": torch.float64, "i32": torch.int32}[dtype_name]
+    if t.dtype != dt or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what}: need a contiguous {dtype_name} CUDA tensor of shape {tuple(shape)}, got "
+                         f"{t.dtype} {tuple(t.shape)} cuda={t.is_cuda} contiguous={t.is_contiguous()}")
+
+
+def _params(lam, gamma, iters, tol=0.0, check_every=1, resume=False):
+    arr = np.ascontiguousarray(np.asarray(lam, dtype=np.float32).ravel())
+    p = ShsParams()
+    p.lambda_ = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    p.lambda_len = arr.size
+    p.gamma = float(gamma)
+    p.iters = int(iters)
+    p.tol = float(tol)
+    p.check_every = int(check_every)
+    p.resume = 1 if resume else 0
+    return p, arr   # keep `arr` alive while p is used
+
+
+# --------------------------------------------------------------------------- C names
+def shs_num_filters(J: int) -> int:
+    return lib().shs_num_filters(J)
+
+
+def shs_plan_create(n: int, channels: int, q: int, J: int, store: str = "f32", device: int = 0) -> "Plan":
+    return Plan(n, channels, q, J, store, device)
+
+
+class Plan:
+    """Owns an shs_plan* (filter bank and twiddles on the device)."""
+
+    def __init__(self, n, channels, q, J, store="f32", device=0):
+        shape = ShsShape(n, channels, q, J, STORE_CODES[store] if isinstance(store, str) else int(store))
+        h = _VP()
+        _check(lib().shs_plan_create(ctypes.byref(shape), device, ctypes.byref(h)), "shs_plan_create")
+        self.handle = h
+        self.n, self.channels, self.q, self.J, self.store, self.device = n, channels, q, J, store, device
+        self.eta = lib().shs_num_filters(J)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.shs_plan_destroy(h)
+            self.handle = None
+
+    # -- sizes
+    def workspace_bytes(self) -> int:
+        return int(lib().shs_workspace_bytes(self.handle))
+
+    def state_bytes(self) -> int:
+        return int(lib().shs_state_bytes(self.handle))
+
+    def new_workspace(self):
+        import torch
+        nb = self.workspace_bytes()
+        return torch.empty((nb + 255) // 256 * 256, dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    # -- entry points (same names as the C ABI, without the shs_ prefix)
+    def filters(self, out, stream=None):
+        _expect(out, (self.eta, self.n, self.n // 2 + 1), "f32", "d_psi")
+        _check(lib().shs_filters(self.handle, _ptr(out), _stream(stream)), "shs_filters")
+        return out
+
+    def datacost(self, img, codebook, out, p: float = 2.0, stream=None):
+        _expect(img, (self.channels, self.n, self.n), "f32", "d_img")
+        _expect(out, (self.q, self.n, self.n), "f32", "d_s")
+        cb = np.ascontiguousarray(np.asarray(codebook, dtype=np.float32).reshape(self.q, self.channels))
+        _check(lib().shs_datacost(self.handle, _ptr(img), cb.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                  float(p), _ptr(out), _stream(stream)), "shs_datacost")
+        return out
+
+    def shearlet_forward(self, f, c, ws, stream=None):
+        count = f.shape[0]
+        _expect(f, (count, self.n, self.n), "f32", "d_f")
+        _expect(c, (count, self.eta, self.n, self.n), "f32", "d_c")
+        _check(lib().shs_shearlet_forward(self.handle, count, _ptr(f), _ptr(c), _ptr(ws), ws.numel(),
+                                          _stream(stream)), "shs_shearlet_forward")
+        return c
+
+    def shearlet_adjoint(self, c, f, ws, stream=None):
+        count = c.shape[0]
+        _expect(c, (count, self.eta, self.n, self.n), "f32", "d_c")
+        _expect(f, (count, self.n, self.n), "f32", "d_f")
+        _check(lib().shs_shearlet_adjoint(self.handle, count, _ptr(c), _ptr(f), _ptr(ws), ws.numel(),
+                                          _stream(stream)), "shs_shearlet_adjoint")
+        return f
+
+    def solve(self, s, ws, lam, gamma, iters, u=None, labels=None, hist=None, want_stats=True,
+              tol=0.0, check_every=1, resume=False, stream=None):
+        _expect(s, (self.q, self.n, self.n), "f32", "d_s")
+        if u is not None:
+            _expect(u, (self.q, self.n, self.n), "f32", "d_u")
+        if labels is not None:
+            _expect(labels, (self.n, self.n), "i32", "d_labels")
+        if hist is not None:
+            _expect(hist, (iters, 4), "f64", "d_hist")
+        prm, keep = _params(lam, gamma, iters, tol, check_every, resume)
+        st = ShsStats()
+        _check(lib().shs_solve(self.handle, ctypes.byref(prm), _ptr(s), _ptr(ws), ws.numel(), _ptr(u),
+                               _ptr(labels), _ptr(hist), ctypes.byref(st) if want_stats else None,
+                               _stream(stream)), "shs_solve")
+        del keep
+        return st.as_dict() if want_stats else None
+
+    def energy(self, s, u, ws, lam, stream=None) -> float:
+        _expect(s, (self.q, self.n, self.n), "f32", "d_s")
+        _expect(u, (self.q, self.n, self.n), "f32", "d_u")
+        prm, keep = _params(lam, 1.0, 0)
+        e = ctypes.c_double()
+        _check(lib().shs_energy(self.handle, ctypes.byref(prm), _ptr(s), _ptr(u), _ptr(ws), ws.numel(),
+                                ctypes.byref(e), _stream(stream)), "shs_energy")
+        del keep
+        return float(e.value)
+
+
+def segment(img, codebook, J, lam, gamma, iters, store="f32", p=2.0, device=0, hist=False):
+    """Convenience: data term + ADMM solve for one image (torch tensor [C][N][N] on the GPU).
+    Returns (u [q][N][N], labels [N][N], stats dict, hist or None)."""
+    import torch
+    C, n, _ = img.shape
+    cb = np.asarray(codebook, dtype=np.float32)
+    q = cb.shape[0]
+    plan = Plan(n, C, q, J, store, device)
+    dev = img.device
+    s = torch.empty((q, n, n), dtype=torch.float32, device=dev)
+    plan.datacost(img, cb, s, p)
+    ws = plan.new_workspace()
+    u = torch.empty((q, n, n), dtype=torch.float32, device=dev)
+    labels = torch.empty((n, n), dtype=torch.int32, device=dev)
+    h = torch.empty((iters, 4), dtype=torch.float64, device=dev) if hist else None
+    stats = plan.solve(s, ws, lam, gamma, iters, u=u, labels=labels, hist=h)
+    return u, labels, stats, h

@@ -1,0 +1,234 @@
+// Device-side FFT building blocks for gfx950 (CDNA4, wave64).
+//
+// The shearlet transform of the paper (Section 2, eq. (wichtig) and the inverse
+// paragraph) is realised by 2-D DFTs; here every 2-D DFT is a pass over rows and a
+// pass over columns, and each 1-D DFT of length L is a Stockham auto-sort FFT run by
+// T = L/R threads that each hold R points in registers:
+//
+//   stage 0   radix R,  reads positions t + r*T (natural order), no twiddle
+//   [stage 1] radix RM, optional middle stage (RM divides R)
+//   stage 2   radix R,  writes positions t + r*T (natural order)
+//
+// so a thread's input positions equal its output positions: a forward FFT, a
+// pointwise product and an inverse FFT chain in registers without extra exchange.
+// Between stages the points travel through LDS.  Inter-stage twiddles come from a
+// table tw[i] = exp(-2 pi i i / NT) (computed in FP64 on the host, rounded to FP32);
+// twiddles inside a register DFT are compile-time constants.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <utility>
+#include <type_traits>
+
+namespace shs {
+
+// ---------------------------------------------------------------- complex helpers
+struct cpx { float x, y; };
+__device__ __forceinline__ cpx mk(float a, float b) { return cpx{a, b}; }
+__device__ __forceinline__ cpx operator+(cpx a, cpx b) { return cpx{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cpx operator-(cpx a, cpx b) { return cpx{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ cpx operator*(cpx a, float s) { return cpx{a.x * s, a.y * s}; }
+__device__ __forceinline__ cpx cmul(cpx a, cpx b) {
+  return cpx{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ cpx cmulc(cpx a, cpx b) {  // a * conj(b)
+  return cpx{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+__device__ __forceinline__ cpx conj(cpx a) { return cpx{a.x, -a.y}; }
+__device__ __forceinline__ cpx mul_i(cpx a) { return cpx{-a.y, a.x}; }      //  i * a
+__device__ __forceinline__ cpx mul_mi(cpx a) { return cpx{a.y, -a.x}; }     // -i * a
+__device__ __forceinline__ cpx ld(const float2* p) { float2 v = *p; return cpx{v.x, v.y}; }
+__device__ __forceinline__ void st(float2* p, cpx v) { *p = make_float2(v.x, v.y); }
+
+// ---------------------------------------------------------------- compile-time loops
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// ---------------------------------------------------------------- constexpr trig
+// cos / sin of 2*pi*e/n for integer e and power-of-two n, by octant reduction and a
+// Taylor series on [0, pi/4] (evaluated by the compiler in double precision).
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double taylor_sin(double x) {
+  double x2 = x * x, term = x, sum = x;
+  for (int k = 1; k < 14; ++k) { term *= -x2 / double((2 * k) * (2 * k + 1)); sum += term; }
+  return sum;
+}
+constexpr double taylor_cos(double x) {
+  double x2 = x * x, term = 1.0, sum = 1.0;
+  for (int k = 1; k < 14; ++k) { term *= -x2 / double((2 * k - 1) * (2 * k)); sum += term; }
+  return sum;
+}
+// cos(2 pi f) for f in [0, 1)
+constexpr double cos2pi_frac(double f) {
+  if (f > 0.5) f = 1.0 - f;                        // cos(2pi f) = cos(2pi(1-f))
+  double sgn = 1.0;
+  if (f > 0.25) { f = 0.5 - f; sgn = -1.0; }       // cos(2pi f) = -cos(2pi(1/2-f))
+  if (f > 0.125) return sgn * taylor_sin(2.0 * kPi * (0.25 - f));
+  return sgn * taylor_cos(2.0 * kPi * f);
+}
+constexpr double cos2pi(int e, int n) {
+  int m = ((e % n) + n) % n;
+  return cos2pi_frac(double(m) / double(n));
+}
+constexpr double sin2pi(int e, int n) {  // sin(2pi e/n) = cos(2pi (e/n - 1/4))
+  return cos2pi(4 * e - n, 4 * n);
+}
+
+// x * W_n^e with W_n = exp(-2 pi i / n) (forward) or its conjugate (inverse).
+template <int E, int NN, bool INV>
+__device__ __forceinline__ cpx twc(cpx x) {
+  constexpr int e = ((E % NN) + NN) % NN;
+  if constexpr (e == 0) {
+    return x;
+  } else if constexpr (4 * e == NN) {
+    return INV ? mul_i(x) : mul_mi(x);
+  } else if constexpr (2 * e == NN) {
+    return cpx{-x.x, -x.y};
+  } else if constexpr (4 * e == 3 * NN) {
+    return INV ? mul_mi(x) : mul_i(x);
+  } else {
+    constexpr float c = float(cos2pi(e, NN));
+    constexpr float s = float(INV ? sin2pi(e, NN) : -sin2pi(e, NN));
+    return cpx{x.x * c - x.y * s, x.x * s + x.y * c};
+  }
+}
+
+// ---------------------------------------------------------------- register DFTs
+// In-place DFT of R points held in registers (natural order in and out), unnormalised,
+// forward = exp(-2 pi i jk/R), inverse = exp(+2 pi i jk/R).
+template <int R, bool INV> struct RegDFT {
+  __device__ __forceinline__ static void run(cpx (&a)[R]);
+};
+
+// R = A * B split in registers (four-step): B-point DFTs over the A interleaved
+// subsequences x[j + A m], twiddle W_R^{j k2}, then A-point DFTs across.
+template <int R, int A, int B, bool INV>
+__device__ __forceinline__ void reg_dft_split(cpx (&a)[R]) {
+  cpx y[A][B];
+  static_for<A>([&](auto j) {
+    static_for<B>([&](auto m) { y[j][m] = a[j + A * m]; });
+    RegDFT<B, INV>::run(y[j]);
+    static_for<B>([&](auto k2) { y[j][k2] = twc<int(j) * int(k2), R, INV>(y[j][k2]); });
+  });
+  static_for<B>([&](auto k2) {
+    cpx z[A];
+    static_for<A>([&](auto j) { z[j] = y[j][k2]; });
+    RegDFT<A, INV>::run(z);
+    static_for<A>([&](auto k1) { a[k2 + B * k1] = z[k1]; });
+  });
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void RegDFT<R, INV>::run(cpx (&a)[R]) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 2) {
+    cpx t = a[0];
+    a[0] = t + a[1];
+    a[1] = t - a[1];
+  } else if constexpr (R == 4) {
+    cpx s0 = a[0] + a[2], d0 = a[0] - a[2];
+    cpx s1 = a[1] + a[3], d1 = a[1] - a[3];
+    d1 = INV ? mul_i(d1) : mul_mi(d1);
+    a[0] = s0 + s1;
+    a[2] = s0 - s1;
+    a[1] = d0 + d1;
+    a[3] = d0 - d1;
+  } else if constexpr (R == 8) {
+    reg_dft_split<8, 2, 4, INV>(a);
+  } else if constexpr (R == 16) {
+    reg_dft_split<16, 4, 4, INV>(a);
+  } else {
+    static_assert(R == 32, "register DFT sizes 1..32");
+    reg_dft_split<32, 4, 8, INV>(a);
+  }
+}
+
+// An FFT of complex length L = R * R * RM (RM = 1 means two stages) is run by T = L / R
+// threads; R and RM are chosen per use (row or column pass) by the caller.
+
+enum SyncKind { SYNC_WAVE = 0, SYNC_BLOCK = 1 };
+
+template <int SK>
+__device__ __forceinline__ void fft_sync() {
+  if constexpr (SK == SYNC_BLOCK) {
+    __syncthreads();
+  } else {
+    // All lanes of one FFT live in one wavefront: order the LDS traffic of the wave.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// Row-style LDS addressing: FFT points contiguous with one pad slot per R points.
+template <int R>
+struct RowAddr {
+  float2* base;
+  __device__ __forceinline__ float2* operator()(int pos) const { return base + pos + pos / R; }
+};
+// Column-style LDS addressing: W FFTs interleaved, point pos of FFT c at pos*W + c.
+template <int W>
+struct ColAddr {
+  float2* base;  // already offset by the column c
+  __device__ __forceinline__ float2* operator()(int pos) const { return base + pos * W; }
+};
+
+// In-register/LDS Stockham FFT of length L.  On entry a[r] holds point t + r*T; on exit
+// a[r] holds output bin t + r*T.  `tw` is the table exp(-2 pi i m / NT), `twstep` = NT / L.
+// The caller must have synchronised any earlier reader of the LDS region before the call
+// (the routine synchronises before its first LDS write).
+template <int L, int R, int RM, bool INV, int SK, class Addr>
+__device__ __forceinline__ void fft_run(cpx (&a)[R], const Addr& lds, int t,
+                                        const float2* __restrict__ tw, int twstep) {
+  static_assert(R * R * RM == L && R % RM == 0, "FFT configuration");
+  constexpr int T = L / R;
+  // stage 0: radix R, Ns = 1
+  RegDFT<R, INV>::run(a);
+  fft_sync<SK>();
+  static_for<R>([&](auto r) { st(lds(t * R + r), a[r]); });
+  fft_sync<SK>();
+  if constexpr (RM > 1) {
+    // middle stage: radix RM, Ns = R; this thread runs R/RM butterflies bf = t + u*T
+    constexpr int U = R / RM;
+    cpx b[R];
+    static_for<U>([&](auto u) {
+      const int bf = t + u * T;
+      static_for<RM>([&](auto r) { b[u * RM + r] = ld(lds(bf + r * (L / RM))); });
+    });
+    fft_sync<SK>();
+    static_for<U>([&](auto u) {
+      const int bf = t + u * T;
+      const int k = bf % R;
+      cpx c[RM];
+      static_for<RM>([&](auto r) {
+        cpx v = b[u * RM + r];
+        if constexpr (r > 0) {
+          cpx w = ld(tw + (r * k) * (L / (R * RM)) * twstep);
+          v = INV ? cmulc(v, w) : cmul(v, w);
+        }
+        c[r] = v;
+      });
+      RegDFT<RM, INV>::run(c);
+      const int obase = (bf / R) * (R * RM) + k;
+      static_for<RM>([&](auto r) { st(lds(obase + r * R), c[r]); });
+    });
+    fft_sync<SK>();
+  }
+  // last stage: radix R, Ns = L/R, butterfly bf = t, k = t
+  static_for<R>([&](auto r) {
+    cpx v = ld(lds(t + r * T));
+    if constexpr (r > 0) {
+      cpx w = ld(tw + (r * t) * twstep);
+      v = INV ? cmulc(v, w) : cmul(v, w);
+    }
+    a[r] = v;
+  });
+  RegDFT<R, INV>::run(a);
+}
+
+}  // namespace shs

@@ -1,0 +1,665 @@
+// HIP kernels for gfx950 implementing the ADMM hot path of the shearlet-regularised
+// multi-label segmentation (Haeuser & Steidl, arXiv 1112.1805, Sections 2-3).
+//
+// Data layout (all row-major):
+//   real images          [channel][N][N]          float (state: float / bf16 / f16)
+//   half spectra         [channel][N][P] float2   bins (k0, k1), k1 = 0..N/2, P >= N/2+1
+//   filter bank          [eta][N][P]     float    real spectra on the half grid
+// A 2-D DFT is a row pass (real <-> half spectrum along k1) and a column pass (complex
+// FFT along k0).  The row pass of the ADMM fuses: inverse row FFT of the synthesised
+// coefficient spectrum, the shrinkage/multiplier update of the state, and the forward
+// row FFT of the next adjoint input, so the state is read and written once per
+// iteration.  Column passes stream strips of W adjacent columns (coalesced) and loop
+// over filters with the spectrum of u (synthesis) or the adjoint accumulator (analysis)
+// held in registers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft.hpp"
+
+namespace shs {
+
+// ---------------------------------------------------------------- storage types
+enum StoreKind { ST_F32 = 0, ST_BF16 = 1, ST_F16 = 2 };
+
+__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+__device__ __forceinline__ uint16_t f_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return uint16_t((u >> 16) | 0x40);  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return uint16_t(u >> 16);
+}
+__device__ __forceinline__ float f16_to_f(uint16_t h) {
+  _Float16 v = __builtin_bit_cast(_Float16, h);
+  return float(v);
+}
+__device__ __forceinline__ uint16_t f_to_f16(float f) {
+  _Float16 v = _Float16(f);
+  return __builtin_bit_cast(uint16_t, v);
+}
+
+// Load / store a pixel pair (x, x+1), x even, of a state image.
+template <int ST> struct Store;
+template <> struct Store<ST_F32> {
+  using T = float;
+  __device__ __forceinline__ static void load2(const T* p, float& a, float& b) {
+    float2 v = *reinterpret_cast<const float2*>(p); a = v.x; b = v.y;
+  }
+  __device__ __forceinline__ static void store2(T* p, float a, float b) {
+    *reinterpret_cast<float2*>(p) = make_float2(a, b);
+  }
+  __device__ __forceinline__ static float round(float a) { return a; }
+};
+template <> struct Store<ST_BF16> {
+  using T = uint16_t;
+  __device__ __forceinline__ static void load2(const T* p, float& a, float& b) {
+    uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+    a = bf16_to_f(uint16_t(v & 0xffffu)); b = bf16_to_f(uint16_t(v >> 16));
+  }
+  __device__ __forceinline__ static void store2(T* p, float a, float b) {
+    *reinterpret_cast<uint32_t*>(p) = uint32_t(f_to_bf16(a)) | (uint32_t(f_to_bf16(b)) << 16);
+  }
+  __device__ __forceinline__ static float round(float a) { return bf16_to_f(f_to_bf16(a)); }
+};
+template <> struct Store<ST_F16> {
+  using T = uint16_t;
+  __device__ __forceinline__ static void load2(const T* p, float& a, float& b) {
+    uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+    a = f16_to_f(uint16_t(v & 0xffffu)); b = f16_to_f(uint16_t(v >> 16));
+  }
+  __device__ __forceinline__ static void store2(T* p, float a, float b) {
+    *reinterpret_cast<uint32_t*>(p) = uint32_t(f_to_f16(a)) | (uint32_t(f_to_f16(b)) << 16);
+  }
+  __device__ __forceinline__ static float round(float a) { return f16_to_f(f_to_f16(a)); }
+};
+
+// ---------------------------------------------------------------- FP64 block reduction
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// Deterministic sum of 4 values over a block of NWAVES waves; result valid in thread 0.
+template <int NWAVES>
+__device__ __forceinline__ void block_sum4(double (&v)[4], double* sh) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = wave_sum(v[i]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sh[wave * 4 + i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < NWAVES; ++w) s += sh[w * 4 + i];
+      v[i] = s;
+    }
+  }
+}
+// Partial-sum slots: 0 = |dy|^2, 1 = |db|^2, 2 = <w, s>, 3 = sum lambda |v| (or energy l1).
+enum { SLOT_DY2 = 0, SLOT_DB2 = 1, SLOT_WS = 2, SLOT_L1 = 3 };
+
+// ---------------------------------------------------------------- filter bank (FP64)
+// Meyer building blocks of Section 2 (eq. (psi1_psi2), the auxiliary polynomial v, the
+// profile b and the scaling-function profile), evaluated in double precision.
+__device__ __forceinline__ double mey_v(double x) {
+  if (x < 0.0) return 0.0;
+  if (x > 1.0) return 1.0;
+  const double x2 = x * x;
+  return x2 * x2 * (35.0 + x * (-84.0 + x * (70.0 - 20.0 * x)));
+}
+__device__ __forceinline__ double mey_b(double x) {
+  const double a = fabs(x);
+  if (a >= 1.0 && a <= 2.0) return sin(0.5 * M_PI * mey_v(a - 1.0));
+  if (a > 2.0 && a <= 4.0) return cos(0.5 * M_PI * mey_v(0.5 * a - 1.0));
+  return 0.0;
+}
+__device__ __forceinline__ double mey_psi1(double w) {
+  const double b2 = mey_b(2.0 * w), b1 = mey_b(w);
+  return sqrt(b2 * b2 + b1 * b1);
+}
+__device__ __forceinline__ double mey_psi2(double w) { return w <= 0.0 ? sqrt(mey_v(1.0 + w)) : sqrt(mey_v(1.0 - w)); }
+__device__ __forceinline__ double mey_phi(double w) {
+  const double a = fabs(w);
+  if (a <= 0.5) return 1.0;
+  if (a < 1.0) return cos(0.5 * M_PI * mey_v(2.0 * a - 1.0));
+  return 0.0;
+}
+
+// Decode filter index f (documented order) into kind (0 low, 1 h, 2 v, 3 seam), scale, shear.
+__device__ __forceinline__ void decode_filter(int f, int& kind, int& j, int& k) {
+  if (f == 0) { kind = 0; j = 0; k = 0; return; }
+  int rem = f - 1;
+  j = 0;
+  while (rem >= (4 << j)) { rem -= (4 << j); ++j; }
+  const int ns = (2 << j) - 1;      // shears per cone at scale j
+  const int half = (1 << j) - 1;
+  if (rem < ns) { kind = 1; k = rem - half; }
+  else if (rem < 2 * ns) { kind = 2; k = rem - ns - half; }
+  else { kind = 3; k = (rem == 2 * ns) ? -(1 << j) : (1 << j); }
+}
+
+// psi1(4^-j a) psi2(2^j b/a + k): the sheared, dilated shearlet of Section 2 (a != 0).
+__device__ __forceinline__ double shear_val(double a, double b, int j, int k) {
+  return mey_psi1(a / double(1 << (2 * j))) * mey_psi2(double(1 << j) * b / a + double(k));
+}
+
+// Filter value at integer frequencies (o1, o2) with xi = rho * omega.
+__device__ double filter_value(int kind, int j, int k, int o1, int o2, double rho) {
+  const double x1 = rho * o1, x2 = rho * o2;
+  const int a1 = o1 < 0 ? -o1 : o1, a2 = o2 < 0 ? -o2 : o2;
+  if (kind == 0) return mey_phi(fmax(fabs(x1), fabs(x2)));
+  double v = 0.0;
+  if (kind != 2 && a2 < a1) v += shear_val(x1, x2, j, k);         // horizontal cone
+  if (kind != 1 && a1 < a2) v += shear_val(x2, x1, j, k);         // vertical cone
+  if (kind == 3 && a1 == a2 && a1 > 0) v += shear_val(x1, x2, j, k);  // seam line
+  return v;
+}
+
+__device__ __forceinline__ int freq_of(int idx, int n) { return idx < (n + 1) / 2 ? idx : idx - n; }
+
+// One thread per (filter, k0, k1) of the half spectrum (k1 <= N/2).
+__global__ void k_filter_gen(float* __restrict__ psi, int n, int J, int P, int eta) {
+  const int half = n / 2 + 1;
+  const long long total = (long long)eta * n * half;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int k1 = int(i % half);
+  const int k0 = int((i / half) % n);
+  const int f = int(i / ((long long)half * n));
+  int kind, j, k;
+  decode_filter(f, kind, j, k);
+  const double rho = double(1 << (2 * J)) / double(n);
+  const int o1 = freq_of(k0, n), o2 = freq_of(k1, n);
+  double v = filter_value(kind, j, k, o1, o2, rho);
+  if ((n % 2 == 0) && (k0 == n / 2 || k1 == n / 2)) {
+    // Nyquist bins: energy-symmetrise with the mirror bin -omega (mod N).
+    const int m0 = (n - k0) % n, m1 = (n - k1) % n;
+    const double w = filter_value(kind, j, k, freq_of(m0, n), freq_of(m1, n), rho);
+    v = sqrt(0.5 * (v * v + w * w));
+  }
+  psi[((long long)f * n + k0) * P + k1] = float(v);
+}
+
+// ---------------------------------------------------------------- data term
+struct Codebook { float c[8 * 4]; };
+// s[k][p] = sum_c |f[c][p] - cb[k][c]|^p (eq. (computationOfs), colour form of Section 4).
+__global__ void k_datacost(const float* __restrict__ img, int C, Codebook cb, int q, float pw,
+                           float* __restrict__ s, long long n2) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n2) return;
+  float f[4];
+  for (int c = 0; c < C; ++c) f[c] = img[c * n2 + i];
+  for (int k = 0; k < q; ++k) {
+    float acc = 0.f;
+    for (int c = 0; c < C; ++c) {
+      const float d = f[c] - cb.c[k * 4 + c];
+      acc += (pw == 2.0f) ? d * d : powf(fabsf(d), pw);
+    }
+    s[k * n2 + i] = acc;
+  }
+}
+
+// ---------------------------------------------------------------- row pass
+enum RowMode { ROW_SOLVE = 0, ROW_C2R = 1, ROW_R2C = 2, ROW_PRIME = 3, ROW_ENERGY = 4 };
+
+// Row FFTs have complex length M = N/2: (R, RM) with R * R * RM = M.
+template <int M> struct RowFft;
+template <> struct RowFft<32>   { static constexpr int R = 4,  RM = 2; };
+template <> struct RowFft<64>   { static constexpr int R = 8,  RM = 1; };
+template <> struct RowFft<128>  { static constexpr int R = 8,  RM = 2; };
+template <> struct RowFft<256>  { static constexpr int R = 16, RM = 1; };
+template <> struct RowFft<512>  { static constexpr int R = 16, RM = 2; };
+template <> struct RowFft<1024> { static constexpr int R = 32, RM = 1; };
+
+template <int N> struct RowGeom {
+  static constexpr int M = N / 2;
+  static constexpr int R = RowFft<M>::R;
+  static constexpr int RM = RowFft<M>::RM;
+  static constexpr int T = M / R;
+  static constexpr int RPW = 64 / T;          // rows per wave
+  static constexpr int WAVES = 4;
+  static constexpr int RPB = RPW * WAVES;     // rows per block
+  static constexpr int LROW = M + M / R;      // LDS float2 per row (padded)
+};
+
+constexpr int kMaxFilters = 256;
+struct FilterWeights {
+  float thr[kMaxFilters];   // per-filter threshold gamma * lambda_j
+  float lam[kMaxFilters];   // per-filter weight lambda_j
+};
+
+struct RowParams {
+  const float2* spec_in;   // half spectra read (SOLVE, C2R, ENERGY)
+  float2* spec_out;        // half spectra written (SOLVE, R2C, PRIME)
+  const float* real_in;    // real rows read (R2C)
+  float* real_out;         // real rows written (C2R)
+  void* g;                 // ADMM state g_v (SOLVE, PRIME)
+  const float2* tw;        // exp(-2 pi i m / N), m < N
+  double* partials;        // [blocks][4] FP64 partial sums (STATS)
+  long long spec_cs;       // channel stride of spectra (float2)
+  long long real_cs;       // channel stride of real rows (floats)
+  int P;                   // spectrum row pitch
+  int eta;                 // filters per label: filter of channel ch is ch % eta
+  int emit;                // SOLVE: write the next adjoint input spectrum
+  FilterWeights fw;        // passed by value (kernel argument memory)
+};
+
+// Inverse real FFT of a half-spectrum row (unnormalised): X[0..M] -> x[0..N) with
+// point pair (2p, 2p+1) of p = t + r*T in a[r] = (x[2p], x[2p+1]).
+template <int N, class Addr>
+__device__ __forceinline__ void row_c2r(cpx (&a)[RowGeom<N>::R], const float2* __restrict__ X,
+                                        const Addr& A, int t, const float2* __restrict__ tw) {
+  using G = RowGeom<N>;
+  static_for<G::R>([&](auto r) {
+    const int k = t + r * G::T;
+    const cpx xp = ld(X + k);
+    const cpx xm = conj(ld(X + (G::M - k)));
+    const cpx s = xp + xm, d = xp - xm;
+    const cpx w = conj(ld(tw + k));          // W_N^{-k}
+    a[r] = s + mul_i(cmul(d, w));
+  });
+  fft_run<G::M, G::R, G::RM, true, SYNC_WAVE>(a, A, t, tw, 2);
+}
+
+// Forward real FFT of a row held as pairs a[r] = (x[2p], x[2p+1]); writes X[0..M].
+template <int N, class Addr>
+__device__ __forceinline__ void row_r2c(cpx (&a)[RowGeom<N>::R], float2* __restrict__ X, const Addr& A,
+                                        int t, const float2* __restrict__ tw) {
+  using G = RowGeom<N>;
+  fft_run<G::M, G::R, G::RM, false, SYNC_WAVE>(a, A, t, tw, 2);
+  fft_sync<SYNC_WAVE>();
+  static_for<G::R>([&](auto r) { st(A(t + r * G::T), a[r]); });
+  fft_sync<SYNC_WAVE>();
+  static_for<G::R>([&](auto r) {
+    const int k = t + r * G::T;
+    const cpx yk = a[r];
+    const cpx ym = conj(ld(A((G::M - k) & (G::M - 1))));
+    const cpx s = yk + ym, d = yk - ym;
+    const cpx w = ld(tw + k);                 // W_N^{k}
+    st(X + k, (s - mul_i(cmul(d, w))) * 0.5f);
+  });
+  if (t == 0) st(X + G::M, cpx{a[0].x - a[0].y, 0.f});
+}
+
+template <int N, int MODE, int ST, bool STATS>
+__global__ __launch_bounds__(256) void k_row(RowParams p) {
+  using G = RowGeom<N>;
+  using S = Store<ST>;
+  __shared__ float2 lds[G::RPB * G::LROW];
+  __shared__ double red[4 * 4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = lane / G::T, t = lane % G::T;
+  const int rowl = wave * G::RPW + sub;
+  const int row = blockIdx.x * G::RPB + rowl;
+  const int ch = blockIdx.y;
+  const int j = ch % p.eta;
+  const RowAddr<G::R> A{lds + rowl * G::LROW};
+  cpx a[G::R];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+
+  if constexpr (MODE == ROW_SOLVE || MODE == ROW_C2R || MODE == ROW_ENERGY) {
+    row_c2r<N>(a, p.spec_in + ch * p.spec_cs + (long long)row * p.P, A, t, p.tw);
+  }
+  if constexpr (MODE == ROW_C2R) {
+    float* out = p.real_out + ch * p.real_cs + (long long)row * N;
+    static_for<G::R>([&](auto r) {
+      const int k = t + r * G::T;
+      *reinterpret_cast<float2*>(out + 2 * k) = make_float2(a[r].x, a[r].y);
+    });
+    return;
+  }
+  if constexpr (MODE == ROW_ENERGY) {
+    static_for<G::R>([&](auto r) { acc[SLOT_L1] += double(fabsf(a[r].x)) + double(fabsf(a[r].y)); });
+    acc[SLOT_L1] *= double(p.fw.lam[j]);
+  }
+  if constexpr (MODE == ROW_R2C) {
+    const float* in = p.real_in + ch * p.real_cs + (long long)row * N;
+    static_for<G::R>([&](auto r) {
+      const int k = t + r * G::T;
+      const float2 v = *reinterpret_cast<const float2*>(in + 2 * k);
+      a[r] = cpx{v.x, v.y};
+    });
+  }
+  if constexpr (MODE == ROW_SOLVE || MODE == ROW_PRIME) {
+    typename S::T* gp = reinterpret_cast<typename S::T*>(p.g) + (long long)ch * N * N + (long long)row * N;
+    const float th = p.fw.thr[j];
+    static_for<G::R>([&](auto r) {
+      const int k = t + r * G::T;
+      float g0, g1;
+      S::load2(gp + 2 * k, g0, g1);
+      const float b0 = fminf(fmaxf(g0, -th), th), b1 = fminf(fmaxf(g1, -th), th);
+      float n0 = g0, n1 = g1;
+      if constexpr (MODE == ROW_SOLVE) {
+        // g <- clip(g) + S_j u  (v = shrink(g), b_v = clip(g); Section 3 v- and b_v-updates)
+        n0 = S::round(b0 + a[r].x);
+        n1 = S::round(b1 + a[r].y);
+        S::store2(gp + 2 * k, n0, n1);
+      }
+      const float nb0 = fminf(fmaxf(n0, -th), th), nb1 = fminf(fmaxf(n1, -th), th);
+      if constexpr (STATS && MODE == ROW_SOLVE) {
+        const float dv0 = (n0 - nb0) - (g0 - b0), dv1 = (n1 - nb1) - (g1 - b1);
+        const float db0 = nb0 - b0, db1 = nb1 - b1;
+        acc[SLOT_DY2] += double(dv0) * dv0 + double(dv1) * dv1;
+        acc[SLOT_DB2] += double(db0) * db0 + double(db1) * db1;
+        acc[SLOT_L1] += double(fabsf(n0 - nb0)) + double(fabsf(n1 - nb1));
+      }
+      // next adjoint input v - b_v = g - 2 clip(g)
+      a[r] = cpx{n0 - 2.f * nb0, n1 - 2.f * nb1};
+    });
+    if constexpr (STATS && MODE == ROW_SOLVE) acc[SLOT_L1] *= double(p.fw.lam[j]);
+  }
+  if constexpr (MODE == ROW_R2C || MODE == ROW_PRIME || MODE == ROW_SOLVE) {
+    bool emit = true;
+    if constexpr (MODE == ROW_SOLVE) emit = p.emit != 0;
+    if (emit) row_r2c<N>(a, p.spec_out + ch * p.spec_cs + (long long)row * p.P, A, t, p.tw);
+  }
+  if constexpr (STATS) {
+    block_sum4<G::WAVES>(acc, red);
+    if (threadIdx.x == 0) {
+      double* o = p.partials + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * 4;
+      o[0] = acc[0]; o[1] = acc[1]; o[2] = acc[2]; o[3] = acc[3];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- column passes
+// Column FFTs have complex length N: radix R (and middle radix RM), W adjacent columns
+// per block (W * 8 bytes contiguous per row segment), W * T threads.
+template <int N> struct ColGeom;
+template <> struct ColGeom<64>   { static constexpr int R = 8,  RM = 1, W = 16; };
+template <> struct ColGeom<128>  { static constexpr int R = 8,  RM = 2, W = 16; };
+template <> struct ColGeom<256>  { static constexpr int R = 16, RM = 1, W = 16; };
+template <> struct ColGeom<512>  { static constexpr int R = 16, RM = 2, W = 16; };
+template <> struct ColGeom<1024> { static constexpr int R = 16, RM = 4, W = 8; };
+template <> struct ColGeom<2048> { static constexpr int R = 16, RM = 8, W = 4; };
+template <int N> struct ColCfg : ColGeom<N> {
+  static constexpr int T = N / ColGeom<N>::R;
+  static constexpr int THREADS = ColGeom<N>::W * T;
+};
+
+struct ColParams {
+  const float2* in;       // spectra read
+  float2* out;            // spectra written
+  const float* psi;       // filter bank [eta][N][P]
+  const float2* tw;       // exp(-2 pi i m / N)
+  float2* accp;           // analysis partial accumulators [nchunks][labels][N][P]
+  int P, eta, fc, nchunks, labels;
+  float inv_n2;           // 1 / N^2 (normalisation of the inverse 2-D DFT)
+};
+
+// Synthesis: per label l and column strip, U = colFFT(V_l) kept in registers; for each
+// filter j of the block's chunk: colIFFT(psi_j * U / N^2) -> T1[l*eta + j].
+template <int N>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_syn(ColParams p) {
+  using G = ColCfg<N>;
+  constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
+  __shared__ float2 lds[N * W];
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int k1 = blockIdx.x * W + c;
+  const bool valid = k1 <= M;
+  const int l = blockIdx.y;
+  const int j0 = blockIdx.z * p.fc, j1 = min(j0 + p.fc, p.eta);
+  const ColAddr<W> A{lds + c};
+  const long long plane = (long long)N * p.P;
+  cpx uh[R];
+  const float2* V = p.in + l * plane;
+  static_for<R>([&](auto r) {
+    const int k0 = t + r * T;
+    uh[r] = valid ? ld(V + (long long)k0 * p.P + k1) : cpx{0.f, 0.f};
+  });
+  fft_run<N, R, G::RM, false, SYNC_BLOCK>(uh, A, t, p.tw, 1);
+  for (int j = j0; j < j1; ++j) {
+    const float* ps = p.psi + j * plane;
+    cpx a[R];
+    static_for<R>([&](auto r) {
+      const int k0 = t + r * T;
+      const float f = valid ? ps[(long long)k0 * p.P + k1] : 0.f;
+      a[r] = uh[r] * (f * p.inv_n2);
+    });
+    fft_run<N, R, G::RM, true, SYNC_BLOCK>(a, A, t, p.tw, 1);
+    float2* o = p.out + ((long long)l * p.eta + j) * plane;
+    if (valid) {
+      static_for<R>([&](auto r) { st(o + (long long)(t + r * T) * p.P + k1, a[r]); });
+    }
+  }
+}
+
+// Analysis: per label l and strip, ACC = sum_j psi_j * colFFT(T2[l*eta + j]) over the
+// block's chunk; with one chunk, Z = colIFFT(ACC / N^2) directly, otherwise the chunk's
+// partial accumulator is written and k_col_final sums the chunks.
+template <int N>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_ana(ColParams p) {
+  using G = ColCfg<N>;
+  constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
+  __shared__ float2 lds[N * W];
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int k1 = blockIdx.x * W + c;
+  const bool valid = k1 <= M;
+  const int l = blockIdx.y;
+  const int j0 = blockIdx.z * p.fc, j1 = min(j0 + p.fc, p.eta);
+  const ColAddr<W> A{lds + c};
+  const long long plane = (long long)N * p.P;
+  cpx acc[R];
+  static_for<R>([&](auto r) { acc[r] = cpx{0.f, 0.f}; });
+  for (int j = j0; j < j1; ++j) {
+    const float2* in = p.in + ((long long)l * p.eta + j) * plane;
+    cpx a[R];
+    static_for<R>([&](auto r) {
+      const int k0 = t + r * T;
+      a[r] = valid ? ld(in + (long long)k0 * p.P + k1) : cpx{0.f, 0.f};
+    });
+    fft_run<N, R, G::RM, false, SYNC_BLOCK>(a, A, t, p.tw, 1);
+    const float* ps = p.psi + j * plane;
+    static_for<R>([&](auto r) {
+      const int k0 = t + r * T;
+      const float f = valid ? ps[(long long)k0 * p.P + k1] : 0.f;
+      acc[r] = acc[r] + a[r] * f;
+    });
+  }
+  if (p.nchunks == 1) {
+    static_for<R>([&](auto r) { acc[r] = acc[r] * p.inv_n2; });
+    fft_run<N, R, G::RM, true, SYNC_BLOCK>(acc, A, t, p.tw, 1);
+    float2* o = p.out + l * plane;
+    if (valid) {
+      static_for<R>([&](auto r) { st(o + (long long)(t + r * T) * p.P + k1, acc[r]); });
+    }
+  } else {
+    float2* o = p.accp + ((long long)blockIdx.z * p.labels + l) * plane;
+    if (valid) {
+      static_for<R>([&](auto r) { st(o + (long long)(t + r * T) * p.P + k1, acc[r]); });
+    }
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_final(ColParams p) {
+  using G = ColCfg<N>;
+  constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
+  __shared__ float2 lds[N * W];
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int k1 = blockIdx.x * W + c;
+  const bool valid = k1 <= M;
+  const int l = blockIdx.y;
+  const ColAddr<W> A{lds + c};
+  const long long plane = (long long)N * p.P;
+  cpx acc[R];
+  static_for<R>([&](auto r) { acc[r] = cpx{0.f, 0.f}; });
+  for (int z = 0; z < p.nchunks; ++z) {
+    const float2* in = p.accp + ((long long)z * p.labels + l) * plane;
+    static_for<R>([&](auto r) {
+      const int k0 = t + r * T;
+      if (valid) acc[r] = acc[r] + ld(in + (long long)k0 * p.P + k1);
+    });
+  }
+  static_for<R>([&](auto r) { acc[r] = acc[r] * p.inv_n2; });
+  fft_run<N, R, G::RM, true, SYNC_BLOCK>(acc, A, t, p.tw, 1);
+  float2* o = p.out + l * plane;
+  if (valid) {
+    static_for<R>([&](auto r) { st(o + (long long)(t + r * T) * p.P + k1, acc[r]); });
+  }
+}
+
+// ---------------------------------------------------------------- per-pixel u / w step
+struct PixParams {
+  const float* z;      // S^T (v - b_v) per label [q][N^2] (null on the first iteration)
+  float* w;            // w   [q][N^2]  (read, written)
+  float* bw;           // b_w [q][N^2]  (read, written)
+  const float* s;      // data term [q][N^2]
+  float* u;            // u   [q][N^2]  (written)
+  double* partials;    // [blocks][4]
+  long long n2;
+  float gamma;
+  int q;
+};
+
+// u = 1/2 [z + (w - b_w) - gamma s]  (Section 3 u-update, A^T A = 2I);
+// g_w = b_w + u;  w = P_C(g_w) (pixelwise simplex);  b_w = g_w - w.
+// The projection follows the paper's procedure: project onto the hyperplane sum = 1,
+// drop the entries that are not positive, re-project the rest, until none is dropped.
+template <bool STATS, bool HAVE_Z>
+__global__ __launch_bounds__(256) void k_pixel(PixParams p) {
+  constexpr int MQ = 8;
+  __shared__ double red[4 * 4];
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const bool active = i < p.n2;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (active) {
+    float gw[MQ], wo[MQ], bo[MQ], sv[MQ];
+#pragma unroll
+    for (int l = 0; l < MQ; ++l) {
+      if (l < p.q) {
+        const long long o = l * p.n2 + i;
+        const float z = HAVE_Z ? p.z[o] : 0.f;
+        wo[l] = p.w[o]; bo[l] = p.bw[o]; sv[l] = p.s[o];
+        const float u = 0.5f * (z + (wo[l] - bo[l]) - p.gamma * sv[l]);
+        p.u[o] = u;
+        gw[l] = bo[l] + u;
+      }
+    }
+    bool act[MQ];
+    int cnt = p.q;
+#pragma unroll
+    for (int l = 0; l < MQ; ++l) act[l] = l < p.q;
+    float tau = 0.f;
+    for (int round = 0; round < MQ; ++round) {
+      float sum = 0.f;
+#pragma unroll
+      for (int l = 0; l < MQ; ++l) sum += act[l] ? gw[l] : 0.f;
+      tau = (sum - 1.f) / float(cnt);
+      bool dropped = false;
+#pragma unroll
+      for (int l = 0; l < MQ; ++l) {
+        if (act[l] && gw[l] - tau <= 0.f) { act[l] = false; --cnt; dropped = true; }
+      }
+      if (!dropped) break;
+    }
+#pragma unroll
+    for (int l = 0; l < MQ; ++l) {
+      if (l < p.q) {
+        const long long o = l * p.n2 + i;
+        const float wn = act[l] ? gw[l] - tau : 0.f;
+        const float bn = gw[l] - wn;
+        p.w[o] = wn;
+        p.bw[o] = bn;
+        if constexpr (STATS) {
+          const float dw = wn - wo[l], db = bn - bo[l];
+          acc[SLOT_DY2] += double(dw) * dw;
+          acc[SLOT_DB2] += double(db) * db;
+          acc[SLOT_WS] += double(wn) * double(sv[l]);
+        }
+      }
+    }
+  }
+  if constexpr (STATS) {
+    block_sum4<4>(acc, red);
+    if (threadIdx.x == 0) {
+      double* o = p.partials + (long long)blockIdx.x * 4;
+      o[0] = acc[0]; o[1] = acc[1]; o[2] = acc[2]; o[3] = acc[3];
+    }
+  }
+}
+
+// <u, s> partial sums (energy), one per block.
+__global__ __launch_bounds__(256) void k_dot(const float* __restrict__ u, const float* __restrict__ s,
+                                             long long n, double* partials) {
+  __shared__ double red[4 * 4];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    acc[SLOT_WS] += double(u[i]) * double(s[i]);
+  block_sum4<4>(acc, red);
+  if (threadIdx.x == 0) {
+    double* o = partials + (long long)blockIdx.x * 4;
+    o[0] = acc[0]; o[1] = acc[1]; o[2] = acc[2]; o[3] = acc[3];
+  }
+}
+
+// Relaxed labelling and label map: u* = w, label = first index of the largest entry.
+__global__ __launch_bounds__(256) void k_epilogue(const float* __restrict__ w, int q, long long n2,
+                                                  float* __restrict__ u_out, int32_t* __restrict__ labels) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n2) return;
+  float best = w[i];
+  int arg = 0;
+  if (u_out) u_out[i] = best;
+  for (int l = 1; l < q; ++l) {
+    const float v = w[l * n2 + i];
+    if (u_out) u_out[l * n2 + i] = v;
+    if (v > best) { best = v; arg = l; }
+  }
+  if (labels) labels[i] = arg;
+}
+
+// ---------------------------------------------------------------- reductions
+// Level 1: block b sums partial rows [b*per, min((b+1)*per, n)) in a fixed order.
+__global__ __launch_bounds__(256) void k_reduce1(const double* __restrict__ parts, long long n, long long per,
+                                                 double* __restrict__ out) {
+  __shared__ double red[4 * 4];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const long long b0 = blockIdx.x * per, b1 = min(b0 + per, n);
+  for (long long r = b0 + threadIdx.x; r < b1; r += 256) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] += parts[r * 4 + i];
+  }
+  block_sum4<4>(acc, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[blockIdx.x * 4 + i] = acc[i];
+  }
+}
+
+// Level 2: one block; writes totals[0..3], the history row (r_primal, r_dual, r_combined,
+// surrogate energy) and a non-finite flag in totals[4].
+__global__ __launch_bounds__(256) void k_reduce2(const double* __restrict__ in, int n, double* __restrict__ totals,
+                                                 double* __restrict__ hist_row, double gamma) {
+  __shared__ double red[4 * 4];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int r = threadIdx.x; r < n; r += 256) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] += in[r * 4 + i];
+  }
+  block_sum4<4>(acc, red);
+  if (threadIdx.x == 0) {
+    const double dy2 = acc[SLOT_DY2], db2 = acc[SLOT_DB2];
+    totals[0] = acc[0]; totals[1] = acc[1]; totals[2] = acc[2]; totals[3] = acc[3];
+    const double comb = dy2 + db2;
+    totals[4] = (isfinite(comb) && isfinite(acc[2]) && isfinite(acc[3])) ? 0.0 : 1.0;
+    if (hist_row) {
+      hist_row[0] = sqrt(db2);
+      hist_row[1] = sqrt(dy2) / gamma;
+      hist_row[2] = comb;
+      hist_row[3] = acc[SLOT_WS] + acc[SLOT_L1];
+    }
+  }
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, long long n, float v) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace shs
