@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Benchmark of the shearlet-segmentation ADMM hot path on one MI355X.
+
+One step = one complete segmentation solve of the workload: data term, `iters` ADMM
+iterations (shearlet adjoint, u-update, simplex projection, shearlet forward, shrinkage and
+multiplier updates, FP64 residual reductions every iteration), the label-map epilogue and
+the exact final energy.  Inputs are resident in HBM before the timed region; the plan
+(filter bank) is built once before it.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ADMM iters/s and Mpixel·label·filter/s at 1024² K=5 J=4; %HBM roofline"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VALU_PEAK_TFS = 157.3     # MI355X FP32 vector (FMA counted)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "row_solve_c2_f16_traffic.md")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1112_1805_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".hpp", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(d, name), "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "shearseg.h"), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def workload(name: str):
+    from synth import make_c0, make_c1, make_c2, make_c4
+    return {"c0": make_c0, "c1": make_c1, "c2": make_c2, "c4": make_c4}[name]()
+
+
+def describe(w, store, iters):
+    kind = "RGB" if w.channels == 3 else "gray"
+    return (f"{w.name}: {w.n}x{w.n} {kind} synthetic segmentation, q={w.q} labels, J={w.J} "
+            f"({1 + 4 * (2 ** w.J - 1)} shearlet filters), {iters} ADMM iterations, gamma={w.gamma}, "
+            f"Lambda={[round(float(x), 6) for x in w.lam]}, {store} coefficient/multiplier state, "
+            f"FP32 FFT math, FP64 reductions")
+
+
+def read_traffic(kernel_hash: str):
+    """Counter-measured HBM bytes per launch of the row_solve kernel, if the committed
+    summary was taken on the current kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    mh = re.search(r"source_hash:\s*([0-9a-f]+)", txt)
+    mb = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not mh or not mb or mh.group(1) != kernel_hash:
+        return None
+    return float(mb.group(1))
+
+
+def run_gpu(args, w, store, iters, steps, warmup, profile):
+    import torch
+    import paper_1112_1805_amd as pkg
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    plan = pkg.Plan(w.n, w.channels, w.q, w.J, store, 0)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    img = torch.tensor(w.img, dtype=torch.float32, device=dev)
+    s = torch.empty((w.q, w.n, w.n), dtype=torch.float32, device=dev)
+    ws = plan.new_workspace()
+    u = torch.empty((w.q, w.n, w.n), dtype=torch.float32, device=dev)
+    labels = torch.empty((w.n, w.n), dtype=torch.int32, device=dev)
+    hist = None if args.no_hist else torch.empty((iters, 4), dtype=torch.float64, device=dev)
+    stats = None
+
+    def step():
+        plan.datacost(img, w.codebook, s)
+        return plan.solve(s, ws, w.lam, w.gamma, iters, u=u, labels=labels, hist=hist, want_stats=True)
+
+    for i in range(warmup):
+        stats = step()
+        log(f"warmup {i + 1}/{warmup} done ({store})")
+    torch.cuda.synchronize()
+    if profile:
+        pkg.shs_profile_begin()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        stats = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = pkg.shs_profile_end() if profile else None
+    log(f"timed {steps} steps ({store}): {dt:.3f}s")
+    return dict(seconds=dt, plan_ms=plan_ms, stats=stats, prof=prof, ws_bytes=plan.workspace_bytes(),
+                eta=plan.eta, labels=labels, u=u)
+
+
+def kernel_units(w, iters, eta, store_bytes):
+    """Algorithmic bytes / flops per launch of each kernel class (one launch per iteration)."""
+    n, q = w.n, w.q
+    lg = (2 * n).bit_length() - 2        # log2(N) for power-of-two N
+    rfft_row = 2.5 * n * lg              # real FFT of length N (conventional count)
+    cfft_col = 5.0 * n * lg              # complex FFT of length N
+    half = n // 2 + 1
+    return {
+        # state g read + written once (the v / b_v update, Section 3)
+        "row_solve": ("hbm", 2.0 * store_bytes * eta * q * n * n, "GB/s"),
+        "col_syn": ("alu", eta * q * half * cfft_col + q * half * cfft_col, "TFLOP/s"),
+        "col_ana": ("alu", eta * q * half * cfft_col + q * half * cfft_col, "TFLOP/s"),
+        # u-update, simplex and b_w update: read z, w, b_w, s, write u, w, b_w
+        "pixel": ("hbm", 7.0 * 4 * q * n * n, "GB/s"),
+        "row_c2r": ("alu", q * n * rfft_row, "TFLOP/s"),
+        "row_r2c": ("alu", q * n * rfft_row, "TFLOP/s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c4"])
+    ap.add_argument("--store", default="f16", choices=["f32", "bf16", "f16"])
+    ap.add_argument("--iters", type=int, default=None, help="ADMM iterations per step (default: workload's)")
+    ap.add_argument("--cpu-iters", type=int, default=1, help="oracle iterations timed for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f32", action="store_true", help="skip the plain FP32 path run beside the main one")
+    ap.add_argument("--no-hist", action="store_true",
+                    help="residual reductions on the last iteration only (default: every iteration)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the run, copy a 1 GiB buffer once (HBM counter calibration for rocprofv3 --pmc)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on exactly one GPU (the path has no multi-GPU mode); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = workload(args.workload)
+    iters = args.iters if args.iters is not None else w.iters
+    store_bytes = 4 if args.store == "f32" else 2
+    log(f"workload {w.name} n={w.n} q={w.q} J={w.J} iters={iters} store={args.store}")
+
+    main_run = run_gpu(args, w, args.store, iters, args.steps, args.warmup, profile=True)
+    eta = main_run["eta"]
+    sec = main_run["seconds"]
+    its = args.steps * iters / sec
+    mplf = its * w.n * w.n * w.q * eta / 1e6
+
+    # ---- roofline of the dominant kernel (event-timed inside the timed region)
+    prof = main_run["prof"]
+    units = kernel_units(w, iters, eta, store_bytes)
+    breakdown = {k: {"launches": n, "total_ms": round(ms, 4), "avg_ms": round(ms / max(n, 1), 5)}
+                 for k, (n, ms) in prof.items()}
+    dominant = max((k for k in prof if k in units), key=lambda k: prof[k][1])
+    bound, amount, unit = units[dominant]
+    n_launch, tot_ms = prof[dominant]
+    avg_s = tot_ms / n_launch / 1e3
+    achieved = amount / avg_s / (1e9 if unit == "GB/s" else 1e12)
+    peak = HBM_PEAK_GBS if unit == "GB/s" else FP32_VALU_PEAK_TFS
+    khash = source_hash()
+    traffic = read_traffic(khash) if (dominant == "row_solve" and args.workload == "c2" and args.store == "f16"
+                                      and iters == w.iters) else None
+    roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": dominant,
+                "algorithmic_per_launch": amount, "avg_launch_ms": round(avg_s * 1e3, 5)}
+    # row_solve is also reported when it is not the dominant kernel
+    rs = prof.get("row_solve")
+    row_solve_hbm = None
+    if rs:
+        b = units["row_solve"][1]
+        row_solve_hbm = {"avg_launch_ms": round(rs[1] / rs[0], 5),
+                         "achieved_GBs": round(b / (rs[1] / rs[0] / 1e3) / 1e9, 1),
+                         "frac": round(b / (rs[1] / rs[0] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    # whole-iteration roofline: algorithmic bytes per iteration over the iteration time
+    bytes_iter = 2.0 * store_bytes * eta * w.q * w.n * w.n + 12.0 * w.q * w.n * w.n
+    iter_hbm_frac = bytes_iter * its / 1e9 / HBM_PEAK_GBS
+
+    st = main_run["stats"]
+    out = {
+        "metric": METRIC,
+        "value": round(its, 3),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": describe(w, args.store, iters), "image": f"{w.n}x{w.n}x{w.channels}",
+                   "labels": w.q, "scales": w.J, "filters": eta, "iters_per_step": iters,
+                   "state_storage": args.store},
+        "mpixel_label_filter_per_s": round(mplf, 1),
+        "ms_per_iter": round(sec / args.steps / iters * 1e3, 4),
+        "iteration_hbm_frac": round(iter_hbm_frac, 4),
+        "roofline": roofline,
+        "row_solve_hbm": row_solve_hbm,
+        "kernel_breakdown_ms": breakdown,
+        "plan_create_ms": round(main_run["plan_ms"], 2),
+        "final_stats": {k: (round(v, 9) if isinstance(v, float) else v) for k, v in st.items()},
+        "source_hash": khash,
+    }
+
+    if not args.no_f32 and args.store != "f32":
+        f32 = run_gpu(args, w, "f32", iters, 1, 1, profile=False)
+        f32_its = iters / f32["seconds"]
+        agree = float((f32["labels"] == main_run["labels"]).float().mean().item())
+        du = float((f32["u"] - main_run["u"]).abs().max().item())
+        e32 = f32["stats"]["energy"]
+        out["f32_path"] = {"iters_per_s": round(f32_its, 3), "ms_per_iter": round(1e3 / f32_its, 4),
+                           "energy": e32, "label_agreement_vs_main": agree, "max_abs_u_diff_vs_main": du,
+                           "energy_rel_diff_vs_main": abs(st["energy"] - e32) / abs(e32)}
+        del f32
+
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = {"read": a.numel() * 4, "write": b.numel() * 4}
+        del a, b
+
+    if not args.no_cpu_baseline:
+        workers = min(16, os.cpu_count() or 1)
+        os.environ["ORACLE_FFT_WORKERS"] = str(workers)
+        import numpy as np
+        import oracle
+        oracle.transform.WORKERS = workers
+        s64 = oracle.datacost(np.float32(w.img).astype(np.float64), np.float32(w.codebook).astype(np.float64))
+        B = oracle.filter_bank(w.n, w.J)
+        lam_f = oracle.lambda_per_filter(w.lam, w.J)
+        log(f"cpu baseline: oracle, {args.cpu_iters} iterations, {workers} FFT workers")
+        t0 = time.perf_counter()
+        oracle.admm(s64, B, lam_f, w.gamma, args.cpu_iters)
+        cdt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": round(args.cpu_iters / cdt, 6), "unit": "iters/s", "cores": workers, "kind": "oracle",
+            "sample": (f"{args.cpu_iters} ADMM iterations of the same workload from the zero state, FP64 "
+                       f"numpy/scipy oracle ({workers} scipy.fft workers, numpy elementwise ops on one "
+                       f"thread); {cdt:.1f} s"),
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -160,6 +160,20 @@ shs_status shs_solve(const shs_plan* plan, const shs_params* params, const float
 shs_status shs_energy(const shs_plan* plan, const shs_params* params, const float* d_s, const float* d_u,
                       void* d_ws, size_t ws_bytes, double* h_energy, void* stream);
 
+/* ---- optional kernel timing (benchmarks) ------------------------------------------
+ * Between shs_profile_begin() and shs_profile_end(), every kernel the library enqueues is
+ * bracketed by a pair of HIP events recorded on the stream it is launched on.
+ * shs_profile_end() waits for those events and returns, per kernel class, the number of
+ * launches and the summed event-measured duration; it returns the number of classes
+ * written (<= max_entries) or -1 on error.  Process-wide; not for concurrent solves. */
+typedef struct {
+  char name[32];       /* kernel class: row_solve, col_syn, col_ana, col_final, row_c2r, ... */
+  int64_t launches;
+  double total_ms;
+} shs_kernel_time;
+shs_status shs_profile_begin(void);
+int32_t shs_profile_end(shs_kernel_time* out, int32_t max_entries);
+
 const char* shs_status_str(shs_status status);
 const char* shs_last_error(void);
 

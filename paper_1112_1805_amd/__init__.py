@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libshearseg.so")
+LIB_PATH = os.environ.get("SHEARSEG_LIB") or os.path.join(_HERE, "libshearseg.so")
 
 SHS_OK, SHS_E_INVALID, SHS_E_UNSUPPORTED, SHS_E_NOMEM, SHS_E_DEVICE, SHS_E_NUMERIC, SHS_E_WORKSPACE = \
     0, -1, -2, -3, -4, -5, -6
@@ -42,6 +42,10 @@ class ShsStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ShsKernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
 class ShsError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         super().__init__(f"{where}: status {status} ({detail})")
@@ -64,6 +68,8 @@ _SIGS = {
                          ctypes.POINTER(ShsStats), _VP]),
     "shs_energy": (_I32, [_VP, ctypes.POINTER(ShsParams), _VP, _VP, _VP, _SZ,
                           ctypes.POINTER(ctypes.c_double), _VP]),
+    "shs_profile_begin": (_I32, []),
+    "shs_profile_end": (_I32, [ctypes.POINTER(ShsKernelTime), _I32]),
     "shs_status_str": (ctypes.c_char_p, [_I32]),
     "shs_last_error": (ctypes.c_char_p, []),
 }
@@ -126,6 +132,19 @@ def _params(lam, gamma, iters, tol=0.0, check_every=1, resume=False):
 # --------------------------------------------------------------------------- C names
 def shs_num_filters(J: int) -> int:
     return lib().shs_num_filters(J)
+
+
+def shs_profile_begin() -> None:
+    _check(lib().shs_profile_begin(), "shs_profile_begin")
+
+
+def shs_profile_end() -> dict:
+    """{kernel class: (launches, total event-measured ms)} since shs_profile_begin()."""
+    buf = (ShsKernelTime * 32)()
+    k = lib().shs_profile_end(buf, 32)
+    if k < 0:
+        raise ShsError(-4, "shs_profile_end", lib().shs_last_error().decode())
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(k)}
 
 
 def shs_plan_create(n: int, channels: int, q: int, J: int, store: str = "f32", device: int = 0) -> "Plan":

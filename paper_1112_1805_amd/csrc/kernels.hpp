@@ -24,11 +24,12 @@ namespace shs {
 enum StoreKind { ST_F32 = 0, ST_BF16 = 1, ST_F16 = 2 };
 
 __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
-__device__ __forceinline__ uint16_t f_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return uint16_t((u >> 16) | 0x40);  // NaN
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-  return uint16_t(u >> 16);
+// float -> bf16, round to nearest even (the gfx950 conversion instruction)
+__device__ __forceinline__ uint16_t f_to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t f2_to_bf16x2(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){a, b}, bf16x2_t));
 }
 __device__ __forceinline__ float f16_to_f(uint16_t h) {
   _Float16 v = __builtin_bit_cast(_Float16, h);
@@ -43,9 +44,9 @@ __device__ __forceinline__ uint16_t f_to_f16(float f) {
 template <int ST> struct Store;
 template <> struct Store<ST_F32> {
   using T = float;
-  __device__ __forceinline__ static void load2(const T* p, float& a, float& b) {
-    float2 v = *reinterpret_cast<const float2*>(p); a = v.x; b = v.y;
-  }
+  using Pair = float2;
+  __device__ __forceinline__ static Pair load_pair(const T* p) { return *reinterpret_cast<const float2*>(p); }
+  __device__ __forceinline__ static void unpack(Pair v, float& a, float& b) { a = v.x; b = v.y; }
   __device__ __forceinline__ static void store2(T* p, float a, float b) {
     *reinterpret_cast<float2*>(p) = make_float2(a, b);
   }
@@ -53,19 +54,21 @@ template <> struct Store<ST_F32> {
 };
 template <> struct Store<ST_BF16> {
   using T = uint16_t;
-  __device__ __forceinline__ static void load2(const T* p, float& a, float& b) {
-    uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+  using Pair = uint32_t;
+  __device__ __forceinline__ static Pair load_pair(const T* p) { return *reinterpret_cast<const uint32_t*>(p); }
+  __device__ __forceinline__ static void unpack(Pair v, float& a, float& b) {
     a = bf16_to_f(uint16_t(v & 0xffffu)); b = bf16_to_f(uint16_t(v >> 16));
   }
   __device__ __forceinline__ static void store2(T* p, float a, float b) {
-    *reinterpret_cast<uint32_t*>(p) = uint32_t(f_to_bf16(a)) | (uint32_t(f_to_bf16(b)) << 16);
+    *reinterpret_cast<uint32_t*>(p) = f2_to_bf16x2(a, b);
   }
   __device__ __forceinline__ static float round(float a) { return bf16_to_f(f_to_bf16(a)); }
 };
 template <> struct Store<ST_F16> {
   using T = uint16_t;
-  __device__ __forceinline__ static void load2(const T* p, float& a, float& b) {
-    uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+  using Pair = uint32_t;
+  __device__ __forceinline__ static Pair load_pair(const T* p) { return *reinterpret_cast<const uint32_t*>(p); }
+  __device__ __forceinline__ static void unpack(Pair v, float& a, float& b) {
     a = f16_to_f(uint16_t(v & 0xffffu)); b = f16_to_f(uint16_t(v >> 16));
   }
   __device__ __forceinline__ static void store2(T* p, float a, float b) {
@@ -204,6 +207,33 @@ __global__ void k_datacost(const float* __restrict__ img, int C, Codebook cb, in
   }
 }
 
+// ---------------------------------------------------------------- strip geometry
+// Column FFTs have complex length N: radix R (and middle radix RM), one strip of W
+// adjacent columns per block, W * T threads.  Strip s holds columns [s W, s W + W) (only
+// those <= N/2 exist).  Strips are stored as contiguous blocks, so W only trades block
+// size against occupancy (W = 4 at N = 1024: 256 threads, 32 KB LDS, 3 blocks per CU).
+template <int N> struct ColGeom;
+template <> struct ColGeom<64>   { static constexpr int R = 8,  RM = 1, W = 16; };
+template <> struct ColGeom<128>  { static constexpr int R = 8,  RM = 2, W = 16; };
+template <> struct ColGeom<256>  { static constexpr int R = 16, RM = 1, W = 16; };
+template <> struct ColGeom<512>  { static constexpr int R = 16, RM = 2, W = 8; };
+template <> struct ColGeom<1024> { static constexpr int R = 16, RM = 4, W = 4; };
+template <> struct ColGeom<2048> { static constexpr int R = 16, RM = 8, W = 4; };
+template <int N> struct ColCfg : ColGeom<N> {
+  static constexpr int T = N / ColGeom<N>::R;
+  static constexpr int THREADS = ColGeom<N>::W * T;
+};
+
+// Half-spectrum planes are stored in strips: strip s of a plane (columns [s W, s W + W))
+// is one contiguous block of N * W bins, bin (k0, k1) at k0 * W + (k1 mod W).  A column
+// pass streams a whole block; a row pass (8 consecutive rows per block) reads 8 * W
+// contiguous bins per strip.
+template <int N>
+__device__ __forceinline__ long long tix(int ip, int row) {
+  constexpr int W = ColGeom<N>::W;
+  return (long long)(ip / W) * (N * W) + row * W + (ip & (W - 1));
+}
+
 // ---------------------------------------------------------------- row pass
 enum RowMode { ROW_SOLVE = 0, ROW_C2R = 1, ROW_R2C = 2, ROW_PRIME = 3, ROW_ENERGY = 4 };
 
@@ -214,7 +244,7 @@ template <> struct RowFft<64>   { static constexpr int R = 8,  RM = 1; };
 template <> struct RowFft<128>  { static constexpr int R = 8,  RM = 2; };
 template <> struct RowFft<256>  { static constexpr int R = 16, RM = 1; };
 template <> struct RowFft<512>  { static constexpr int R = 16, RM = 2; };
-template <> struct RowFft<1024> { static constexpr int R = 32, RM = 1; };
+template <> struct RowFft<1024> { static constexpr int R = 16, RM = 4; };
 
 template <int N> struct RowGeom {
   static constexpr int M = N / 2;
@@ -233,32 +263,53 @@ struct FilterWeights {
   float lam[kMaxFilters];   // per-filter weight lambda_j
 };
 
+// A family of half-spectrum planes.  Plane (l, f) at base + l * ls + off_f keeps the
+// columns [cb_f, cb_f + pitch_f) (whole strips, cb_f and pitch_f multiples of W) in strip
+// blocks: bin (k0, k1) at tix(k1 - cb_f, k0).  The filtered spectra (synthesis input /
+// adjoint output of filter f) keep only the strips where filter f is nonzero (wedge
+// pruning); per-label spectra are dense (one plane, cb 0, all P = NS * W columns).
+struct SpecLayout {
+  const int4* tab;   // per filter {cb, pitch, off_lo, off_hi}; null = dense
+  long long ls;      // label stride (float2)
+  int nf;            // planes per label (eta, or 1 when dense)
+  int P;             // columns of a dense plane (NS * W)
+};
+__device__ __forceinline__ void plane_geom(const SpecLayout& L, int f, int& cb, int& pitch, long long& off) {
+  if (L.tab) {
+    const int4 e = L.tab[f];
+    cb = e.x; pitch = e.y; off = (long long)(unsigned)e.z | ((long long)e.w << 32);
+  } else {
+    cb = 0; pitch = L.P; off = 0;
+  }
+}
+
 struct RowParams {
   const float2* spec_in;   // half spectra read (SOLVE, C2R, ENERGY)
   float2* spec_out;        // half spectra written (SOLVE, R2C, PRIME)
+  SpecLayout lin, lout;    // their layouts
   const float* real_in;    // real rows read (R2C)
   float* real_out;         // real rows written (C2R)
   void* g;                 // ADMM state g_v (SOLVE, PRIME)
   const float2* tw;        // exp(-2 pi i m / N), m < N
   double* partials;        // [blocks][4] FP64 partial sums (STATS)
-  long long spec_cs;       // channel stride of spectra (float2)
   long long real_cs;       // channel stride of real rows (floats)
-  int P;                   // spectrum row pitch
   int eta;                 // filters per label: filter of channel ch is ch % eta
   int emit;                // SOLVE: write the next adjoint input spectrum
   FilterWeights fw;        // passed by value (kernel argument memory)
 };
 
 // Inverse real FFT of a half-spectrum row (unnormalised): X[0..M] -> x[0..N) with
-// point pair (2p, 2p+1) of p = t + r*T in a[r] = (x[2p], x[2p+1]).
+// point pair (2p, 2p+1) of p = t + r*T in a[r] = (x[2p], x[2p+1]).  The row holds the
+// columns [cb, cb + pitch); other bins are zero.
 template <int N, class Addr>
-__device__ __forceinline__ void row_c2r(cpx (&a)[RowGeom<N>::R], const float2* __restrict__ X,
-                                        const Addr& A, int t, const float2* __restrict__ tw) {
+__device__ __forceinline__ void row_c2r(cpx (&a)[RowGeom<N>::R], const float2* __restrict__ X, int row, int cb,
+                                        int pitch, const Addr& A, int t, const float2* __restrict__ tw) {
   using G = RowGeom<N>;
   static_for<G::R>([&](auto r) {
     const int k = t + r * G::T;
-    const cpx xp = ld(X + k);
-    const cpx xm = conj(ld(X + (G::M - k)));
+    const unsigned ip = unsigned(k - cb), im = unsigned(G::M - k - cb);
+    const cpx xp = ip < unsigned(pitch) ? ld(X + tix<N>(int(ip), row)) : cpx{0.f, 0.f};
+    const cpx xm = im < unsigned(pitch) ? conj(ld(X + tix<N>(int(im), row))) : cpx{0.f, 0.f};
     const cpx s = xp + xm, d = xp - xm;
     const cpx w = conj(ld(tw + k));          // W_N^{-k}
     a[r] = s + mul_i(cmul(d, w));
@@ -266,10 +317,11 @@ __device__ __forceinline__ void row_c2r(cpx (&a)[RowGeom<N>::R], const float2* _
   fft_run<G::M, G::R, G::RM, true, SYNC_WAVE>(a, A, t, tw, 2);
 }
 
-// Forward real FFT of a row held as pairs a[r] = (x[2p], x[2p+1]); writes X[0..M].
+// Forward real FFT of a row held as pairs a[r] = (x[2p], x[2p+1]); writes the bins of
+// X[0..M] that fall in [cb, cb + pitch).
 template <int N, class Addr>
-__device__ __forceinline__ void row_r2c(cpx (&a)[RowGeom<N>::R], float2* __restrict__ X, const Addr& A,
-                                        int t, const float2* __restrict__ tw) {
+__device__ __forceinline__ void row_r2c(cpx (&a)[RowGeom<N>::R], float2* __restrict__ X, int row, int cb, int pitch,
+                                        const Addr& A, int t, const float2* __restrict__ tw) {
   using G = RowGeom<N>;
   fft_run<G::M, G::R, G::RM, false, SYNC_WAVE>(a, A, t, tw, 2);
   fft_sync<SYNC_WAVE>();
@@ -277,13 +329,16 @@ __device__ __forceinline__ void row_r2c(cpx (&a)[RowGeom<N>::R], float2* __restr
   fft_sync<SYNC_WAVE>();
   static_for<G::R>([&](auto r) {
     const int k = t + r * G::T;
-    const cpx yk = a[r];
-    const cpx ym = conj(ld(A((G::M - k) & (G::M - 1))));
-    const cpx s = yk + ym, d = yk - ym;
-    const cpx w = ld(tw + k);                 // W_N^{k}
-    st(X + k, (s - mul_i(cmul(d, w))) * 0.5f);
+    const unsigned ip = unsigned(k - cb);
+    if (ip < unsigned(pitch)) {
+      const cpx yk = a[r];
+      const cpx ym = conj(ld(A((G::M - k) & (G::M - 1))));
+      const cpx s = yk + ym, d = yk - ym;
+      const cpx w = ld(tw + k);                 // W_N^{k}
+      st(X + tix<N>(int(ip), row), (s - mul_i(cmul(d, w))) * 0.5f);
+    }
   });
-  if (t == 0) st(X + G::M, cpx{a[0].x - a[0].y, 0.f});
+  if (t == 0 && unsigned(G::M - cb) < unsigned(pitch)) st(X + tix<N>(G::M - cb, row), cpx{a[0].x - a[0].y, 0.f});
 }
 
 template <int N, int MODE, int ST, bool STATS>
@@ -300,10 +355,23 @@ __global__ __launch_bounds__(256) void k_row(RowParams p) {
   const int j = ch % p.eta;
   const RowAddr<G::R> A{lds + rowl * G::LROW};
   cpx a[G::R];
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};   // per-thread partial sums of one row segment
+  typename S::T* gp = nullptr;
+  typename S::Pair gv[G::R];
+  if constexpr (MODE == ROW_SOLVE || MODE == ROW_PRIME) {
+    // The state does not depend on the inverse FFT below: load it first so its latency
+    // overlaps the FFT.
+    gp = reinterpret_cast<typename S::T*>(p.g) + (long long)ch * N * N + (long long)row * N;
+    static_for<G::R>([&](auto r) { gv[r] = S::load_pair(gp + 2 * (t + r * G::T)); });
+  }
 
   if constexpr (MODE == ROW_SOLVE || MODE == ROW_C2R || MODE == ROW_ENERGY) {
-    row_c2r<N>(a, p.spec_in + ch * p.spec_cs + (long long)row * p.P, A, t, p.tw);
+    int cb, pitch;
+    long long off;
+    const int f = ch % p.lin.nf;
+    plane_geom(p.lin, f, cb, pitch, off);
+    const float2* X = p.spec_in + (ch / p.lin.nf) * p.lin.ls + off;
+    row_c2r<N>(a, X, row, cb, pitch, A, t, p.tw);
   }
   if constexpr (MODE == ROW_C2R) {
     float* out = p.real_out + ch * p.real_cs + (long long)row * N;
@@ -314,8 +382,7 @@ __global__ __launch_bounds__(256) void k_row(RowParams p) {
     return;
   }
   if constexpr (MODE == ROW_ENERGY) {
-    static_for<G::R>([&](auto r) { acc[SLOT_L1] += double(fabsf(a[r].x)) + double(fabsf(a[r].y)); });
-    acc[SLOT_L1] *= double(p.fw.lam[j]);
+    static_for<G::R>([&](auto r) { acc[SLOT_L1] += fabsf(a[r].x) + fabsf(a[r].y); });
   }
   if constexpr (MODE == ROW_R2C) {
     const float* in = p.real_in + ch * p.real_cs + (long long)row * N;
@@ -326,12 +393,11 @@ __global__ __launch_bounds__(256) void k_row(RowParams p) {
     });
   }
   if constexpr (MODE == ROW_SOLVE || MODE == ROW_PRIME) {
-    typename S::T* gp = reinterpret_cast<typename S::T*>(p.g) + (long long)ch * N * N + (long long)row * N;
     const float th = p.fw.thr[j];
     static_for<G::R>([&](auto r) {
       const int k = t + r * G::T;
       float g0, g1;
-      S::load2(gp + 2 * k, g0, g1);
+      S::unpack(gv[r], g0, g1);
       const float b0 = fminf(fmaxf(g0, -th), th), b1 = fminf(fmaxf(g1, -th), th);
       float n0 = g0, n1 = g1;
       if constexpr (MODE == ROW_SOLVE) {
@@ -344,58 +410,71 @@ __global__ __launch_bounds__(256) void k_row(RowParams p) {
       if constexpr (STATS && MODE == ROW_SOLVE) {
         const float dv0 = (n0 - nb0) - (g0 - b0), dv1 = (n1 - nb1) - (g1 - b1);
         const float db0 = nb0 - b0, db1 = nb1 - b1;
-        acc[SLOT_DY2] += double(dv0) * dv0 + double(dv1) * dv1;
-        acc[SLOT_DB2] += double(db0) * db0 + double(db1) * db1;
-        acc[SLOT_L1] += double(fabsf(n0 - nb0)) + double(fabsf(n1 - nb1));
+        acc[SLOT_DY2] += dv0 * dv0 + dv1 * dv1;
+        acc[SLOT_DB2] += db0 * db0 + db1 * db1;
+        acc[SLOT_L1] += fabsf(n0 - nb0) + fabsf(n1 - nb1);
       }
       // next adjoint input v - b_v = g - 2 clip(g)
       a[r] = cpx{n0 - 2.f * nb0, n1 - 2.f * nb1};
     });
-    if constexpr (STATS && MODE == ROW_SOLVE) acc[SLOT_L1] *= double(p.fw.lam[j]);
+    // Complete the residual partial sums here (an empty asm that reads and writes them):
+    // otherwise the compiler sinks them past the forward FFT and keeps every per-pixel
+    // term live, doubling the register footprint.
+    if constexpr (STATS && MODE == ROW_SOLVE) __asm__ volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[3]));
   }
   if constexpr (MODE == ROW_R2C || MODE == ROW_PRIME || MODE == ROW_SOLVE) {
     bool emit = true;
     if constexpr (MODE == ROW_SOLVE) emit = p.emit != 0;
-    if (emit) row_r2c<N>(a, p.spec_out + ch * p.spec_cs + (long long)row * p.P, A, t, p.tw);
+    if (emit) {
+      int cb, pitch;
+      long long off;
+      const int f = ch % p.lout.nf;
+      plane_geom(p.lout, f, cb, pitch, off);
+      float2* X = p.spec_out + (ch / p.lout.nf) * p.lout.ls + off;
+      row_r2c<N>(a, X, row, cb, pitch, A, t, p.tw);
+    }
   }
   if constexpr (STATS) {
-    block_sum4<G::WAVES>(acc, red);
+    // FP32 partials of one row segment (2R pixels) per thread, FP64 from here on.
+    double d[4] = {double(acc[0]), double(acc[1]), double(acc[2]), double(acc[3])};
+    d[SLOT_L1] *= double(p.fw.lam[j]);
+    block_sum4<G::WAVES>(d, red);
     if (threadIdx.x == 0) {
       double* o = p.partials + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * 4;
-      o[0] = acc[0]; o[1] = acc[1]; o[2] = acc[2]; o[3] = acc[3];
+      o[0] = d[0]; o[1] = d[1]; o[2] = d[2]; o[3] = d[3];
     }
   }
 }
 
 // ---------------------------------------------------------------- column passes
-// Column FFTs have complex length N: radix R (and middle radix RM), W adjacent columns
-// per block (W * 8 bytes contiguous per row segment), W * T threads.
-template <int N> struct ColGeom;
-template <> struct ColGeom<64>   { static constexpr int R = 8,  RM = 1, W = 16; };
-template <> struct ColGeom<128>  { static constexpr int R = 8,  RM = 2, W = 16; };
-template <> struct ColGeom<256>  { static constexpr int R = 16, RM = 1, W = 16; };
-template <> struct ColGeom<512>  { static constexpr int R = 16, RM = 2, W = 16; };
-template <> struct ColGeom<1024> { static constexpr int R = 16, RM = 4, W = 8; };
-template <> struct ColGeom<2048> { static constexpr int R = 16, RM = 8, W = 4; };
-template <int N> struct ColCfg : ColGeom<N> {
-  static constexpr int T = N / ColGeom<N>::R;
-  static constexpr int THREADS = ColGeom<N>::W * T;
-};
-
+// Work item of a column pass: strip, a run of filters (indices into flist) whose
+// column range meets the strip, and the partial-accumulator slot (analysis; -1 when the
+// strip has a single item and the item finalises directly).
 struct ColParams {
   const float2* in;       // spectra read
   float2* out;            // spectra written
-  const float* psi;       // filter bank [eta][N][P]
+  const float* psiw;      // filter values inside each column window (compact)
+  const int4* pwin;       // [eta][N/2+1] {window start a, length L, value offset, 0}
+  SpecLayout tl;          // layout of the filtered spectra (compact)
+  const int4* items;      // {strip, first flist index, count, partial slot}
+  const int* flist;       // filter ids
+  const int2* strips;     // per strip {first analysis item, number of items}
+  float2* part;           // partial accumulators [slot][labels][N][W]
   const float2* tw;       // exp(-2 pi i m / N)
-  float2* accp;           // analysis partial accumulators [nchunks][labels][N][P]
-  int P, eta, fc, nchunks, labels;
+  int P, eta, labels;
   float inv_n2;           // 1 / N^2 (normalisation of the inverse 2-D DFT)
 };
 
-// Synthesis: per label l and column strip, U = colFFT(V_l) kept in registers; for each
-// filter j of the block's chunk: colIFFT(psi_j * U / N^2) -> T1[l*eta + j].
+// psi_j(k0, k1) from the compact window of column k1 (zero outside the window).
 template <int N>
-__global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_syn(ColParams p) {
+__device__ __forceinline__ float psi_at(const ColParams& p, int4 win, int k0) {
+  const unsigned rel = unsigned(k0 - win.x) & unsigned(N - 1);
+  return rel < unsigned(win.y) ? p.psiw[win.z + rel] : 0.f;
+}
+
+// Dense column FFT of per-label spectra: U_l = colFFT(V_l) (forward) on every column.
+template <int N>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_col_fwd(ColParams p) {
   using G = ColCfg<N>;
   constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
   __shared__ float2 lds[N * W];
@@ -403,104 +482,152 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_syn(ColParams p) {
   const int k1 = blockIdx.x * W + c;
   const bool valid = k1 <= M;
   const int l = blockIdx.y;
-  const int j0 = blockIdx.z * p.fc, j1 = min(j0 + p.fc, p.eta);
   const ColAddr<W> A{lds + c};
-  const long long plane = (long long)N * p.P;
+  const long long strip = l * (long long)N * p.P + (long long)blockIdx.x * (N * W) + c;
+  cpx a[R];
+  static_for<R>([&](auto r) { a[r] = valid ? ld(p.in + strip + (t + r * T) * W) : cpx{0.f, 0.f}; });
+  fft_run<N, R, G::RM, false, SYNC_BLOCK>(a, A, t, p.tw, 1);
+  if (valid) {
+    static_for<R>([&](auto r) { st(p.out + strip + (t + r * T) * W, a[r]); });
+  }
+}
+
+// Synthesis: for every filter j of the item, T1[l, j] = colIFFT(psi_j * U_l / N^2) on the
+// item's strip (only columns inside filter j's range exist in T1).
+template <int N>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_col_syn(ColParams p) {
+  using G = ColCfg<N>;
+  constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
+  __shared__ float2 lds[N * W];
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int4 it = p.items[blockIdx.x];
+  const int k1 = it.x * W + c;
+  const bool valid = k1 <= M;
+  const int l = blockIdx.y;
+  const ColAddr<W> A{lds + c};
   cpx uh[R];
-  const float2* V = p.in + l * plane;
-  static_for<R>([&](auto r) {
-    const int k0 = t + r * T;
-    uh[r] = valid ? ld(V + (long long)k0 * p.P + k1) : cpx{0.f, 0.f};
-  });
-  fft_run<N, R, G::RM, false, SYNC_BLOCK>(uh, A, t, p.tw, 1);
-  for (int j = j0; j < j1; ++j) {
-    const float* ps = p.psi + j * plane;
+  const float2* U = p.in + l * (long long)N * p.P + (long long)it.x * (N * W) + c;
+  static_for<R>([&](auto r) { uh[r] = valid ? ld(U + (t + r * T) * W) : cpx{0.f, 0.f}; });
+  for (int i = 0; i < it.z; ++i) {
+    const int j = p.flist[it.y + i];
+    const int4 win = valid ? p.pwin[j * (M + 1) + k1] : make_int4(0, 0, 0, 0);
     cpx a[R];
-    static_for<R>([&](auto r) {
-      const int k0 = t + r * T;
-      const float f = valid ? ps[(long long)k0 * p.P + k1] : 0.f;
-      a[r] = uh[r] * (f * p.inv_n2);
-    });
+    static_for<R>([&](auto r) { a[r] = uh[r] * (psi_at<N>(p, win, t + r * T) * p.inv_n2); });
     fft_run<N, R, G::RM, true, SYNC_BLOCK>(a, A, t, p.tw, 1);
-    float2* o = p.out + ((long long)l * p.eta + j) * plane;
+    int cb, pitch;
+    long long off;
+    plane_geom(p.tl, j, cb, pitch, off);
+    float2* o = p.out + l * p.tl.ls + off + (long long)(it.x - cb / W) * (N * W) + c;
     if (valid) {
-      static_for<R>([&](auto r) { st(o + (long long)(t + r * T) * p.P + k1, a[r]); });
-    }
-  }
-}
-
-// Analysis: per label l and strip, ACC = sum_j psi_j * colFFT(T2[l*eta + j]) over the
-// block's chunk; with one chunk, Z = colIFFT(ACC / N^2) directly, otherwise the chunk's
-// partial accumulator is written and k_col_final sums the chunks.
-template <int N>
-__global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_ana(ColParams p) {
-  using G = ColCfg<N>;
-  constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
-  __shared__ float2 lds[N * W];
-  const int c = threadIdx.x % W, t = threadIdx.x / W;
-  const int k1 = blockIdx.x * W + c;
-  const bool valid = k1 <= M;
-  const int l = blockIdx.y;
-  const int j0 = blockIdx.z * p.fc, j1 = min(j0 + p.fc, p.eta);
-  const ColAddr<W> A{lds + c};
-  const long long plane = (long long)N * p.P;
-  cpx acc[R];
-  static_for<R>([&](auto r) { acc[r] = cpx{0.f, 0.f}; });
-  for (int j = j0; j < j1; ++j) {
-    const float2* in = p.in + ((long long)l * p.eta + j) * plane;
-    cpx a[R];
-    static_for<R>([&](auto r) {
-      const int k0 = t + r * T;
-      a[r] = valid ? ld(in + (long long)k0 * p.P + k1) : cpx{0.f, 0.f};
-    });
-    fft_run<N, R, G::RM, false, SYNC_BLOCK>(a, A, t, p.tw, 1);
-    const float* ps = p.psi + j * plane;
-    static_for<R>([&](auto r) {
-      const int k0 = t + r * T;
-      const float f = valid ? ps[(long long)k0 * p.P + k1] : 0.f;
-      acc[r] = acc[r] + a[r] * f;
-    });
-  }
-  if (p.nchunks == 1) {
-    static_for<R>([&](auto r) { acc[r] = acc[r] * p.inv_n2; });
-    fft_run<N, R, G::RM, true, SYNC_BLOCK>(acc, A, t, p.tw, 1);
-    float2* o = p.out + l * plane;
-    if (valid) {
-      static_for<R>([&](auto r) { st(o + (long long)(t + r * T) * p.P + k1, acc[r]); });
-    }
-  } else {
-    float2* o = p.accp + ((long long)blockIdx.z * p.labels + l) * plane;
-    if (valid) {
-      static_for<R>([&](auto r) { st(o + (long long)(t + r * T) * p.P + k1, acc[r]); });
+      static_for<R>([&](auto r) { st(o + (t + r * T) * W, a[r]); });
     }
   }
 }
 
 template <int N>
-__global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_final(ColParams p) {
+__device__ __forceinline__ void col_finish(const ColParams& p, cpx (&acc)[ColCfg<N>::R], int t, int k1, bool valid,
+                                           int l, const ColAddr<ColCfg<N>::W>& A) {
   using G = ColCfg<N>;
-  constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
-  __shared__ float2 lds[N * W];
-  const int c = threadIdx.x % W, t = threadIdx.x / W;
-  const int k1 = blockIdx.x * W + c;
-  const bool valid = k1 <= M;
-  const int l = blockIdx.y;
-  const ColAddr<W> A{lds + c};
-  const long long plane = (long long)N * p.P;
-  cpx acc[R];
-  static_for<R>([&](auto r) { acc[r] = cpx{0.f, 0.f}; });
-  for (int z = 0; z < p.nchunks; ++z) {
-    const float2* in = p.accp + ((long long)z * p.labels + l) * plane;
-    static_for<R>([&](auto r) {
-      const int k0 = t + r * T;
-      if (valid) acc[r] = acc[r] + ld(in + (long long)k0 * p.P + k1);
-    });
-  }
+  constexpr int R = G::R, T = G::T;
   static_for<R>([&](auto r) { acc[r] = acc[r] * p.inv_n2; });
   fft_run<N, R, G::RM, true, SYNC_BLOCK>(acc, A, t, p.tw, 1);
-  float2* o = p.out + l * plane;
+  float2* o = p.out + l * (long long)N * p.P + (long long)(k1 / G::W) * (N * G::W) + (k1 & (G::W - 1));
   if (valid) {
-    static_for<R>([&](auto r) { st(o + (long long)(t + r * T) * p.P + k1, acc[r]); });
+    static_for<R>([&](auto r) { st(o + (t + r * T) * G::W, acc[r]); });
+  }
+}
+
+// Analysis: ACC = sum_j psi_j * colFFT(T2[l, j]) over the item's filters.  A strip with a
+// single item finishes here (Z_l = colIFFT(ACC / N^2)); otherwise the item's partial
+// accumulator is stored and k_col_final sums the strip's items in order.
+template <int N>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_col_ana(ColParams p) {
+  using G = ColCfg<N>;
+  constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
+  __shared__ float2 lds[N * W];
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int4 it = p.items[blockIdx.x];
+  const int k1 = it.x * W + c;
+  const bool valid = k1 <= M;
+  const int l = blockIdx.y;
+  const ColAddr<W> A{lds + c};
+  cpx acc[R];
+  static_for<R>([&](auto r) { acc[r] = cpx{0.f, 0.f}; });
+  for (int i = 0; i < it.z; ++i) {
+    const int j = p.flist[it.y + i];
+    int cb, pitch;
+    long long off;
+    plane_geom(p.tl, j, cb, pitch, off);
+    const float2* in = p.in + l * p.tl.ls + off + (long long)(it.x - cb / W) * (N * W) + c;
+    cpx a[R];
+    static_for<R>([&](auto r) { a[r] = valid ? ld(in + (t + r * T) * W) : cpx{0.f, 0.f}; });
+    fft_run<N, R, G::RM, false, SYNC_BLOCK>(a, A, t, p.tw, 1);
+    const int4 win = valid ? p.pwin[j * (M + 1) + k1] : make_int4(0, 0, 0, 0);
+    static_for<R>([&](auto r) { acc[r] = acc[r] + a[r] * psi_at<N>(p, win, t + r * T); });
+  }
+  if (it.w < 0) {
+    col_finish<N>(p, acc, t, k1, valid, l, A);
+  } else {
+    float2* o = p.part + ((long long)it.w * p.labels + l) * (N * W);
+    static_for<R>([&](auto r) { st(o + (t + r * T) * W + c, acc[r]); });
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_col_final(ColParams p) {
+  using G = ColCfg<N>;
+  constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
+  __shared__ float2 lds[N * W];
+  const int2 si = p.strips[blockIdx.x];
+  if (si.y <= 1) return;
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int k1 = blockIdx.x * W + c;
+  const bool valid = k1 <= M;
+  const int l = blockIdx.y;
+  const ColAddr<W> A{lds + c};
+  cpx acc[R];
+  static_for<R>([&](auto r) { acc[r] = cpx{0.f, 0.f}; });
+  for (int i = 0; i < si.y; ++i) {
+    const int slot = p.items[si.x + i].w;
+    const float2* in = p.part + ((long long)slot * p.labels + l) * (N * W);
+    static_for<R>([&](auto r) { acc[r] = acc[r] + ld(in + (t + r * T) * W + c); });
+  }
+  col_finish<N>(p, acc, t, k1, valid, l, A);
+}
+
+// ---------------------------------------------------------------- plan-time filter windows
+// For filter j and column k1: the shortest circular interval of k0 holding every nonzero
+// of the column (start a, length L; L = 0 for an all-zero column).
+__global__ void k_filter_windows(const float* __restrict__ psi, int n, int P, int eta, int2* __restrict__ win) {
+  const int half = n / 2 + 1;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= eta * half) return;
+  const int j = i / half, k1 = i % half;
+  const float* col = psi + (long long)j * n * P + k1;
+  int first = -1, last = -1, prev = -1, gap_best = -1, gap_end = 0;
+  for (int k0 = 0; k0 < n; ++k0) {
+    if (col[(long long)k0 * P] != 0.f) {
+      if (first < 0) first = k0;
+      if (prev >= 0 && k0 - prev - 1 > gap_best) { gap_best = k0 - prev - 1; gap_end = k0; }
+      prev = k0;
+      last = k0;
+    }
+  }
+  if (first < 0) { win[i] = make_int2(0, 0); return; }
+  const int wrap = first + n - last - 1;          // zero run across the end of the column
+  if (wrap >= gap_best) win[i] = make_int2(first, last - first + 1);
+  else win[i] = make_int2(gap_end, n - gap_best);
+}
+
+// Gathers the window values: psiw[off + r] = psi[j][(a + r) mod N][k1].
+__global__ void k_filter_compact(const float* __restrict__ psi, int n, int P, int eta, const int4* __restrict__ pwin,
+                                 float* __restrict__ psiw) {
+  const int half = n / 2 + 1;
+  for (int i = blockIdx.y; i < eta * half; i += gridDim.y) {   // (j, k1) pair
+    const int j = i / half, k1 = i % half;
+    const int4 w = pwin[i];
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < w.y; r += gridDim.x * blockDim.x)
+      psiw[w.z + r] = psi[((long long)j * n + ((w.x + r) & (n - 1))) * P + k1];
   }
 }
 

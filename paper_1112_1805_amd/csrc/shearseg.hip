@@ -1,12 +1,13 @@
-// Host side of the shearlet-segmentation library: plan (filter bank + twiddles on the
-// device), workspace layout, launch orchestration of the ADMM of Section 3, and the C ABI
-// declared in include/shearseg.h.
+// Host side of the shearlet-segmentation library: plan (filter bank, its pruned layout
+// and the column work lists on the device), workspace layout, launch orchestration of the
+// ADMM of Section 3, and the C ABI declared in include/shearseg.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -17,9 +18,21 @@
 using namespace shs;
 
 struct shs_plan {
-  int n, C, q, J, store, eta, M, P, device;
-  float* psi;      // [eta][N][P] filter bank (half spectrum)
-  float2* tw;      // [N] exp(-2 pi i m / N)
+  int n, C, q, J, store, eta, M, P, PP, W, NS, device;
+  float* psi;          // [eta][N][PP] dense filter bank (half spectrum)
+  float2* tw;          // [N] exp(-2 pi i m / N)
+  // pruned layout
+  float* psiw;         // filter values inside each column window
+  int4* pwin;          // [eta][M+1] {a, L, value offset, 0}
+  int4* tcol;          // [eta] {cb, pitch, off_lo, off_hi} of the filtered spectra
+  long long t_ls;      // label stride of the filtered spectra (float2)
+  // column work lists
+  int4* items_syn;     // {strip, flist offset, count, -1}
+  int4* items_ana;     // {strip, flist offset, count, partial slot or -1}
+  int* flist;          // filter ids, grouped by strip
+  int2* strips_ana;    // per strip {first analysis item, items}
+  int n_syn, n_ana, n_part;
+  long long nnz;       // stored filter values
 };
 
 namespace {
@@ -59,70 +72,93 @@ struct DeviceGuard {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// ---------------------------------------------------------------- kernel timing
+enum KClass {
+  KC_ROW_SOLVE, KC_COL_SYN, KC_COL_ANA, KC_COL_FINAL, KC_COL_FWD, KC_ROW_C2R, KC_ROW_R2C, KC_ROW_PRIME,
+  KC_ROW_ENERGY, KC_PIXEL, KC_REDUCE, KC_OTHER, KC_COUNT
+};
+const char* const kKClassName[KC_COUNT] = {"row_solve", "col_syn", "col_ana", "col_final", "col_fwd", "row_c2r",
+                                           "row_r2c", "row_prime", "row_energy", "pixel", "reduce", "other"};
+
+struct Prof {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> pool;        // reused across sessions
+  size_t used = 0;
+  std::vector<int> cls;                // class of event pair i (events 2i, 2i+1)
+};
+Prof& prof() {
+  static Prof p;
+  return p;
+}
+
+// Brackets the launches made during its lifetime with HIP events on stream s (when on).
+struct Timed {
+  hipStream_t s;
+  hipEvent_t stop = nullptr;
+  Timed(hipStream_t s_, int cls) : s(s_) {
+    Prof& P = prof();
+    if (!P.on) return;
+    std::lock_guard<std::mutex> g(P.mu);
+    while (P.pool.size() < P.used + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      P.pool.push_back(e);
+    }
+    hipEvent_t start = P.pool[P.used];
+    stop = P.pool[P.used + 1];
+    P.used += 2;
+    P.cls.push_back(cls);
+    (void)hipEventRecord(start, s);
+  }
+  ~Timed() {
+    if (stop) (void)hipEventRecord(stop, s);
+  }
+};
+
 size_t store_bytes(int store) { return store == SHS_STORE_F32 ? 4 : 2; }
 
-int row_rpb(int n) {
+template <template <int> class F>
+int by_size(int n) {
   switch (n) {
-    case 64: return RowGeom<64>::RPB;
-    case 128: return RowGeom<128>::RPB;
-    case 256: return RowGeom<256>::RPB;
-    case 512: return RowGeom<512>::RPB;
-    case 1024: return RowGeom<1024>::RPB;
-    case 2048: return RowGeom<2048>::RPB;
+    case 64: return F<64>::value;
+    case 128: return F<128>::value;
+    case 256: return F<256>::value;
+    case 512: return F<512>::value;
+    case 1024: return F<1024>::value;
+    case 2048: return F<2048>::value;
   }
-  return 1;
+  return 0;
 }
-int col_w(int n) {
-  switch (n) {
-    case 64: return ColGeom<64>::W;
-    case 128: return ColGeom<128>::W;
-    case 256: return ColGeom<256>::W;
-    case 512: return ColGeom<512>::W;
-    case 1024: return ColGeom<1024>::W;
-    case 2048: return ColGeom<2048>::W;
-  }
-  return 1;
-}
+template <int N> struct RpbOf { static constexpr int value = RowGeom<N>::RPB; };
+template <int N> struct WOf { static constexpr int value = ColGeom<N>::W; };
 
 constexpr int kRed1Blocks = 256;
 constexpr int kDotBlocks = 1024;
-constexpr int kTargetBlocks = 2048;   // aim for >> 256 CUs worth of column blocks
 
 struct Layout {
   size_t g, w, bw, state_end;
-  size_t t1, t2, v, z, zs, us, accp, parts, red1, sdev, total;
+  size_t t1, t2, v, z, zs, us, part, parts, red1, sdev, total;
   long long nrow_parts, nparts;
-  int nstrips, fc_syn, nch_syn, fc_ana, nch_ana;
 };
-
-void chunking(int eta, int blocks_per_filterless, int cap, int& fc, int& nch) {
-  int want = (kTargetBlocks + blocks_per_filterless - 1) / blocks_per_filterless;
-  want = std::max(1, std::min(want, std::min(cap, eta)));
-  fc = (eta + want - 1) / want;
-  nch = (eta + fc - 1) / fc;
-}
 
 Layout make_layout(const shs_plan* p) {
   Layout L{};
   const size_t n = p->n, nn = n * n, q = p->q, eta = p->eta, P = p->P;
-  const size_t plane = n * P;  // float2 per spectrum
-  L.nstrips = int(p->M / col_w(p->n) + 1);
-  chunking(p->eta, L.nstrips * p->q, p->eta, L.fc_syn, L.nch_syn);
-  chunking(p->eta, L.nstrips * p->q, 16, L.fc_ana, L.nch_ana);
+  const size_t plane = n * P;  // float2 per dense spectrum
   size_t off = 0;
   L.g = off;   off = align256(off + q * eta * nn * store_bytes(p->store));
   L.w = off;   off = align256(off + q * nn * 4);
   L.bw = off;  off = align256(off + q * nn * 4);
   L.state_end = off;
-  L.t1 = off;  off = align256(off + q * eta * plane * 8);
-  L.t2 = off;  off = align256(off + q * eta * plane * 8);
+  L.t1 = off;  off = align256(off + q * size_t(p->t_ls) * 8);
+  L.t2 = off;  off = align256(off + q * size_t(p->t_ls) * 8);
   L.v = off;   off = align256(off + q * plane * 8);
   L.z = off;   off = align256(off + q * plane * 8);
   L.zs = off;  off = align256(off + q * nn * 4);
   L.us = off;  off = align256(off + q * nn * 4);
-  L.accp = off;
-  if (L.nch_ana > 1) off = align256(off + size_t(L.nch_ana) * q * plane * 8);
-  L.nrow_parts = (long long)(q * eta) * (n / row_rpb(p->n));
+  L.part = off; off = align256(off + size_t(std::max(p->n_part, 1)) * q * n * p->W * 8);
+  L.nrow_parts = (long long)(q * eta) * (n / by_size<RpbOf>(p->n));
   const long long npix = (long long)((nn + 255) / 256);
   L.nparts = L.nrow_parts + std::max<long long>(npix, kDotBlocks);
   L.parts = off; off = align256(off + size_t(L.nparts) * 4 * 8);
@@ -160,24 +196,26 @@ struct Pipe {
       case ROW_ENERGY: row_t<ROW_ENERGY, ST_F32, true>(rp, channels, s); break;
     }
   }
-  static void col_syn(const ColParams& cp, int labels, int nstrips, int nch, hipStream_t s) {
-    hipLaunchKernelGGL((k_col_syn<N>), dim3(nstrips, labels, nch), dim3(CG::THREADS), 0, s, cp);
-  }
-  static void col_ana(const ColParams& cp, int labels, int nstrips, int nch, hipStream_t s) {
-    hipLaunchKernelGGL((k_col_ana<N>), dim3(nstrips, labels, nch), dim3(CG::THREADS), 0, s, cp);
-    if (nch > 1) hipLaunchKernelGGL((k_col_final<N>), dim3(nstrips, labels), dim3(CG::THREADS), 0, s, cp);
+  static void col(int kind, const ColParams& cp, int nblocks, int labels, hipStream_t s) {
+    const dim3 grid(nblocks, labels), block(CG::THREADS);
+    switch (kind) {
+      case 0: hipLaunchKernelGGL((k_col_fwd<N>), grid, block, 0, s, cp); break;
+      case 1: hipLaunchKernelGGL((k_col_syn<N>), grid, block, 0, s, cp); break;
+      case 2: hipLaunchKernelGGL((k_col_ana<N>), grid, block, 0, s, cp); break;
+      case 3: hipLaunchKernelGGL((k_col_final<N>), grid, block, 0, s, cp); break;
+    }
   }
 };
+enum { COL_FWD = 0, COL_SYN = 1, COL_ANA = 2, COL_FINAL = 3 };
 
 struct Ops {
   void (*row)(int, int, bool, const RowParams&, int, hipStream_t);
-  void (*col_syn)(const ColParams&, int, int, int, hipStream_t);
-  void (*col_ana)(const ColParams&, int, int, int, hipStream_t);
+  void (*col)(int, const ColParams&, int, int, hipStream_t);
 };
 
 template <int N>
 Ops ops_for() {
-  return Ops{&Pipe<N>::row, &Pipe<N>::col_syn, &Pipe<N>::col_ana};
+  return Ops{&Pipe<N>::row, &Pipe<N>::col};
 }
 
 bool get_ops(int n, Ops& o) {
@@ -190,6 +228,17 @@ bool get_ops(int n, Ops& o) {
     case 2048: o = ops_for<2048>(); return true;
   }
   return false;
+}
+
+int row_class(int mode) {
+  switch (mode) {
+    case ROW_SOLVE: return KC_ROW_SOLVE;
+    case ROW_C2R: return KC_ROW_C2R;
+    case ROW_R2C: return KC_ROW_R2C;
+    case ROW_PRIME: return KC_ROW_PRIME;
+    case ROW_ENERGY: return KC_ROW_ENERGY;
+  }
+  return KC_OTHER;
 }
 
 // Everything a compute call needs, resolved from plan + workspace.
@@ -215,59 +264,77 @@ shs_status make_ctx(const shs_plan* p, void* ws, size_t ws_bytes, void* stream, 
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(SHS_E_WORKSPACE, "workspace must be 256-byte aligned");
   c.ws = static_cast<char*>(ws);
   c.s = static_cast<hipStream_t>(stream);
+  std::memset(&c.fw, 0, sizeof(c.fw));
   return SHS_OK;
 }
 
-RowParams row_params(const Ctx& c) {
-  RowParams rp{};
+SpecLayout dense_layout(const shs_plan* p) { return SpecLayout{nullptr, (long long)p->n * p->P, 1, p->P}; }
+SpecLayout pruned_layout(const shs_plan* p) { return SpecLayout{p->tcol, p->t_ls, p->eta, p->P}; }
+
+void run_row(const Ctx& c, int mode, int store, bool stats, RowParams rp, int channels) {
   rp.tw = c.p->tw;
-  rp.P = c.p->P;
   rp.eta = c.p->eta;
-  rp.spec_cs = (long long)c.p->n * c.p->P;
   rp.real_cs = (long long)c.p->n * c.p->n;
   rp.fw = c.fw;
   rp.partials = c.at<double>(c.L.parts);
-  rp.emit = 1;
-  return rp;
+  Timed tm(c.s, row_class(mode));
+  c.ops.row(mode, store, stats, rp, channels, c.s);
 }
 
 ColParams col_params(const Ctx& c, int labels) {
+  const shs_plan* p = c.p;
   ColParams cp{};
-  cp.psi = c.p->psi;
-  cp.tw = c.p->tw;
-  cp.accp = c.at<float2>(c.L.accp);
-  cp.P = c.p->P;
-  cp.eta = c.p->eta;
+  cp.psiw = p->psiw;
+  cp.pwin = p->pwin;
+  cp.tl = pruned_layout(p);
+  cp.flist = p->flist;
+  cp.strips = p->strips_ana;
+  cp.part = c.at<float2>(c.L.part);
+  cp.tw = p->tw;
+  cp.P = p->P;
+  cp.eta = p->eta;
   cp.labels = labels;
-  cp.inv_n2 = 1.0f / (float(c.p->n) * float(c.p->n));
+  cp.inv_n2 = 1.0f / (float(p->n) * float(p->n));
   return cp;
 }
 
-// S: real images [count][N][N] -> coefficient spectra T1 (and optionally real coefficients).
-void enqueue_synthesis(const Ctx& c, const float* real_in, int count) {
-  RowParams rp = row_params(c);
-  rp.real_in = real_in;
-  rp.spec_out = c.at<float2>(c.L.v);
-  c.ops.row(ROW_R2C, ST_F32, false, rp, count, c.s);
-  ColParams cp = col_params(c, count);
-  cp.in = c.at<float2>(c.L.v);
-  cp.out = c.at<float2>(c.L.t1);
-  cp.fc = c.L.fc_syn;
-  cp.nchunks = c.L.nch_syn;
-  c.ops.col_syn(cp, count, c.L.nstrips, c.L.nch_syn, c.s);
+void run_col(const Ctx& c, int kind, const ColParams& cp, int nblocks, int labels) {
+  static const int cls[4] = {KC_COL_FWD, KC_COL_SYN, KC_COL_ANA, KC_COL_FINAL};
+  Timed tm(c.s, cls[kind]);
+  c.ops.col(kind, cp, nblocks, labels, c.s);
 }
 
-// Adjoint column side: spectra T2 (count*eta channels) -> Z (count labels).
+// S: real images [count][N][N] -> pruned coefficient spectra T1 (count * eta planes).
+void enqueue_synthesis(const Ctx& c, const float* real_in, int count) {
+  const shs_plan* p = c.p;
+  RowParams rp{};
+  rp.real_in = real_in;
+  rp.spec_out = c.at<float2>(c.L.v);
+  rp.lout = dense_layout(p);
+  run_row(c, ROW_R2C, ST_F32, false, rp, count);
+  ColParams cp = col_params(c, count);
+  cp.in = c.at<float2>(c.L.v);
+  cp.out = c.at<float2>(c.L.v);          // column FFT in place: V -> U
+  run_col(c, COL_FWD, cp, p->NS, count);
+  cp.in = c.at<float2>(c.L.v);
+  cp.out = c.at<float2>(c.L.t1);
+  cp.items = p->items_syn;
+  run_col(c, COL_SYN, cp, p->n_syn, count);
+}
+
+// Adjoint column side: pruned spectra T2 (count * eta planes) -> Z (count dense planes).
 void enqueue_analysis(const Ctx& c, int count) {
+  const shs_plan* p = c.p;
   ColParams cp = col_params(c, count);
   cp.in = c.at<float2>(c.L.t2);
   cp.out = c.at<float2>(c.L.z);
-  cp.fc = c.L.fc_ana;
-  cp.nchunks = c.L.nch_ana;
-  c.ops.col_ana(cp, count, c.L.nstrips, c.L.nch_ana, c.s);
+  cp.items = p->items_ana;
+  run_col(c, COL_ANA, cp, p->n_ana, count);
+  if (p->n_part > 0) run_col(c, COL_FINAL, cp, p->NS, count);
 }
 
 void enqueue_reduce(const Ctx& c, long long nparts, double* hist_row, double gamma) {
+  Timed tm(c.s, KC_REDUCE);
   const long long per = (nparts + kRed1Blocks - 1) / kRed1Blocks;
   hipLaunchKernelGGL(k_reduce1, dim3(kRed1Blocks), dim3(256), 0, c.s, c.at<double>(c.L.parts), nparts,
                      std::max<long long>(per, 1), c.at<double>(c.L.red1));
@@ -304,13 +371,17 @@ shs_status set_lambda(Ctx& c, const shs_params* prm) {
 shs_status energy_of(const Ctx& c, const float* d_u, const float* d_s, double* out) {
   const shs_plan* p = c.p;
   enqueue_synthesis(c, d_u, p->q);
-  RowParams rp = row_params(c);
+  RowParams rp{};
   rp.spec_in = c.at<float2>(c.L.t1);
-  c.ops.row(ROW_ENERGY, ST_F32, true, rp, p->q * p->eta, c.s);
+  rp.lin = pruned_layout(p);
+  run_row(c, ROW_ENERGY, ST_F32, true, rp, p->q * p->eta);
   LAUNCHCHK("energy rows");
   const long long nn = (long long)p->n * p->n * p->q;
-  hipLaunchKernelGGL(k_dot, dim3(kDotBlocks), dim3(256), 0, c.s, d_u, d_s, nn,
-                     c.at<double>(c.L.parts) + c.L.nrow_parts * 4);
+  {
+    Timed tm(c.s, KC_OTHER);
+    hipLaunchKernelGGL(k_dot, dim3(kDotBlocks), dim3(256), 0, c.s, d_u, d_s, nn,
+                       c.at<double>(c.L.parts) + c.L.nrow_parts * 4);
+  }
   enqueue_reduce(c, c.L.nrow_parts + kDotBlocks, nullptr, 1.0);
   LAUNCHCHK("energy reduce");
   double tot[8];
@@ -318,6 +389,111 @@ shs_status energy_of(const Ctx& c, const float* d_u, const float* d_s, double* o
   HIPCHK(hipStreamSynchronize(c.s));
   if (tot[4] != 0.0) return fail(SHS_E_NUMERIC, "non-finite energy");
   *out = tot[SLOT_WS] + tot[SLOT_L1];
+  return SHS_OK;
+}
+
+// ---------------------------------------------------------------- plan construction
+void free_plan(shs_plan* p) {
+  if (!p) return;
+  void* bufs[] = {p->psi, p->tw, p->psiw, p->pwin, p->tcol, p->items_syn, p->items_ana, p->flist, p->strips_ana};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  delete p;
+}
+
+template <class T>
+shs_status upload(T** dst, const std::vector<T>& v) {
+  const size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(T);
+  if (hipMalloc(dst, bytes) != hipSuccess) return fail(SHS_E_NOMEM, "plan table allocation");
+  if (!v.empty()) HIPCHK(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return SHS_OK;
+}
+
+// Column work list: per strip, the filters whose column range meets it, cut into runs of
+// at most `fc` filters.  Analysis lists also assign partial-accumulator slots.
+void build_items(const std::vector<std::vector<int>>& per_strip, const std::vector<int>& strip_flist_off, int fc,
+                 bool with_parts, std::vector<int4>& items, std::vector<int2>* strips, int* nparts) {
+  items.clear();
+  int slot = 0;
+  for (size_t s = 0; s < per_strip.size(); ++s) {
+    const int nf = int(per_strip[s].size());
+    const int nit = (nf + fc - 1) / fc;
+    if (strips) strips->push_back(make_int2(int(items.size()), nit));
+    for (int i = 0; i < nit; ++i) {
+      const int cnt = std::min(fc, nf - i * fc);
+      int part = -1;
+      if (with_parts && nit > 1) part = slot++;
+      items.push_back(make_int4(int(s), strip_flist_off[s] + i * fc, cnt, part));
+    }
+  }
+  if (nparts) *nparts = slot;
+}
+
+shs_status build_pruned_layout(shs_plan* p) {
+  const int n = p->n, half = p->M + 1, eta = p->eta, W = p->W;
+  // 1. column windows of every filter
+  int2* dwin = nullptr;
+  if (hipMalloc(&dwin, size_t(eta) * half * sizeof(int2)) != hipSuccess) return fail(SHS_E_NOMEM, "window scratch");
+  hipLaunchKernelGGL(k_filter_windows, dim3((eta * half + 255) / 256), dim3(256), 0, 0, p->psi, n, p->PP, eta, dwin);
+  std::vector<int2> win(size_t(eta) * half);
+  const hipError_t e1 = hipGetLastError();
+  const hipError_t e2 = hipMemcpy(win.data(), dwin, win.size() * sizeof(int2), hipMemcpyDeviceToHost);
+  (void)hipFree(dwin);
+  if (e1 != hipSuccess || e2 != hipSuccess) return fail(SHS_E_DEVICE, "filter window scan");
+  // 2. compact value offsets and per-filter column ranges (whole strips)
+  std::vector<int4> pwin(win.size());
+  std::vector<int4> tcol(eta);
+  std::vector<int> s0(eta), s1(eta);
+  long long off = 0, toff = 0;
+  for (int j = 0; j < eta; ++j) {
+    int c0 = -1, c1 = -1;
+    for (int k1 = 0; k1 < half; ++k1) {
+      const int2 w = win[size_t(j) * half + k1];
+      pwin[size_t(j) * half + k1] = make_int4(w.x, w.y, int(off), 0);
+      off += w.y;
+      if (w.y > 0) { if (c0 < 0) c0 = k1; c1 = k1; }
+    }
+    if (c0 < 0) c0 = c1 = 0;
+    s0[j] = c0 / W;
+    s1[j] = c1 / W;
+    const int cb = s0[j] * W, pitch = (s1[j] - s0[j] + 1) * W;
+    tcol[j] = make_int4(cb, pitch, int(toff & 0xffffffffLL), int(toff >> 32));
+    toff += (long long)n * pitch;
+  }
+  if (off > 0x7fffffffLL) return fail(SHS_E_UNSUPPORTED, "filter bank too large");
+  p->nnz = off;
+  p->t_ls = toff;
+  // 3. work lists
+  std::vector<std::vector<int>> per_strip(p->NS);
+  std::vector<int> flist, strip_off(p->NS);
+  for (int s = 0; s < p->NS; ++s) {
+    for (int j = 0; j < eta; ++j)
+      if (s >= s0[j] && s <= s1[j]) per_strip[s].push_back(j);
+    strip_off[s] = int(flist.size());
+    flist.insert(flist.end(), per_strip[s].begin(), per_strip[s].end());
+  }
+  const long long pairs = (long long)flist.size();
+  const int fc_syn = int(std::min<long long>(16, std::max<long long>(1, (pairs * p->q + 1249) / 2500)));
+  const int fc_ana = int(std::min<long long>(16, std::max<long long>(2, (pairs * p->q + 749) / 1500)));
+  std::vector<int4> isyn, iana;
+  std::vector<int2> strips;
+  build_items(per_strip, strip_off, fc_syn, false, isyn, nullptr, nullptr);
+  build_items(per_strip, strip_off, fc_ana, true, iana, &strips, &p->n_part);
+  p->n_syn = int(isyn.size());
+  p->n_ana = int(iana.size());
+  shs_status st;
+  if ((st = upload(&p->pwin, pwin)) != SHS_OK) return st;
+  if ((st = upload(&p->tcol, tcol)) != SHS_OK) return st;
+  if ((st = upload(&p->items_syn, isyn)) != SHS_OK) return st;
+  if ((st = upload(&p->items_ana, iana)) != SHS_OK) return st;
+  if ((st = upload(&p->flist, flist)) != SHS_OK) return st;
+  if ((st = upload(&p->strips_ana, strips)) != SHS_OK) return st;
+  // 4. compact filter values
+  if (hipMalloc(&p->psiw, size_t(std::max<long long>(off, 1)) * 4) != hipSuccess) return fail(SHS_E_NOMEM, "psiw");
+  hipLaunchKernelGGL(k_filter_compact, dim3(4, std::min(eta * half, 65535)), dim3(256), 0, 0, p->psi, n, p->PP, eta,
+                     p->pwin, p->psiw);
+  LAUNCHCHK("filter compaction");
+  HIPCHK(hipDeviceSynchronize());
   return SHS_OK;
 }
 
@@ -340,6 +516,44 @@ const char* shs_status_str(shs_status s) {
 }
 
 const char* shs_last_error(void) { return g_err.c_str(); }
+
+shs_status shs_profile_begin(void) {
+  Prof& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  P.on = true;
+  P.used = 0;
+  P.cls.clear();
+  return SHS_OK;
+}
+
+int32_t shs_profile_end(shs_kernel_time* out, int32_t max_entries) {
+  Prof& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  P.on = false;
+  double ms[KC_COUNT] = {0};
+  int64_t cnt[KC_COUNT] = {0};
+  for (size_t i = 0; i < P.cls.size(); ++i) {
+    if (hipEventSynchronize(P.pool[2 * i + 1]) != hipSuccess) { g_err = "event synchronize"; return -1; }
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, P.pool[2 * i], P.pool[2 * i + 1]) != hipSuccess) { g_err = "event elapsed"; return -1; }
+    ms[P.cls[i]] += t;
+    cnt[P.cls[i]] += 1;
+  }
+  int32_t k = 0;
+  for (int c = 0; c < KC_COUNT && k < max_entries; ++c) {
+    if (!cnt[c]) continue;
+    if (out) {
+      std::memset(out[k].name, 0, sizeof(out[k].name));
+      std::strncpy(out[k].name, kKClassName[c], sizeof(out[k].name) - 1);
+      out[k].launches = cnt[c];
+      out[k].total_ms = ms[c];
+    }
+    ++k;
+  }
+  P.used = 0;
+  P.cls.clear();
+  return k;
+}
 
 int32_t shs_num_filters(int32_t J) { return J < 1 || J > 12 ? -1 : 1 + 4 * ((1 << J) - 1); }
 
@@ -366,31 +580,34 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
   p->n = n; p->C = shape->channels; p->q = shape->q; p->J = shape->J; p->store = shape->store;
   p->eta = shs_num_filters(shape->J);
   p->M = n / 2;
-  p->P = p->M + 16;  // 128-byte aligned rows; columns M+1.. are padding
+  p->W = by_size<WOf>(n);
+  p->NS = p->M / p->W + 1;
+  p->P = p->NS * p->W;  // columns of a dense spectrum plane (strip tiled); columns M+1.. unused
+  p->PP = p->M + 16;    // row pitch of the dense filter bank
   p->device = device;
-  const size_t psi_bytes = size_t(p->eta) * n * p->P * 4;
-  if (hipMalloc(&p->psi, psi_bytes) != hipSuccess) { delete p; return fail(SHS_E_NOMEM, "filter bank allocation"); }
-  if (hipMalloc(&p->tw, size_t(n) * 8) != hipSuccess) {
-    (void)hipFree(p->psi); delete p; return fail(SHS_E_NOMEM, "twiddle allocation");
-  }
+  const size_t psi_bytes = size_t(p->eta) * n * p->PP * 4;
+  if (hipMalloc(&p->psi, psi_bytes) != hipSuccess) { free_plan(p); return fail(SHS_E_NOMEM, "filter bank allocation"); }
+  if (hipMalloc(&p->tw, size_t(n) * 8) != hipSuccess) { free_plan(p); return fail(SHS_E_NOMEM, "twiddle allocation"); }
   std::vector<float2> tw(n);
   for (int m = 0; m < n; ++m) {
     const double a = -2.0 * M_PI * double(m) / double(n);
     tw[m] = make_float2(float(std::cos(a)), float(std::sin(a)));
   }
-  shs_status st = SHS_OK;
   if (hipMemcpy(p->tw, tw.data(), size_t(n) * 8, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(p->psi, 0, psi_bytes) != hipSuccess) {
-    st = fail(SHS_E_DEVICE, "plan initialisation copy");
-  } else {
-    const long long total = (long long)p->eta * n * (p->M + 1);
-    hipLaunchKernelGGL(k_filter_gen, dim3(unsigned((total + 255) / 256)), dim3(256), 0, 0, p->psi, n, p->J, p->P,
-                       p->eta);
-    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
-      st = fail(SHS_E_DEVICE, "filter generation failed");
+    free_plan(p);
+    return fail(SHS_E_DEVICE, "plan initialisation copy");
   }
+  const long long total = (long long)p->eta * n * (p->M + 1);
+  hipLaunchKernelGGL(k_filter_gen, dim3(unsigned((total + 255) / 256)), dim3(256), 0, 0, p->psi, n, p->J, p->PP,
+                     p->eta);
+  if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    free_plan(p);
+    return fail(SHS_E_DEVICE, "filter generation failed");
+  }
+  const shs_status st = build_pruned_layout(p);
   if (st != SHS_OK) {
-    (void)hipFree(p->psi); (void)hipFree(p->tw); delete p;
+    free_plan(p);
     return st;
   }
   *out = p;
@@ -400,9 +617,7 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
 shs_status shs_plan_destroy(shs_plan* p) {
   if (!p) return SHS_OK;
   DeviceGuard dg(p->device);
-  (void)hipFree(p->psi);
-  (void)hipFree(p->tw);
-  delete p;
+  free_plan(p);
   return SHS_OK;
 }
 
@@ -413,7 +628,7 @@ shs_status shs_filters(const shs_plan* p, float* d_psi, void* stream) {
   if (!p || !d_psi) return fail(SHS_E_INVALID, "null argument");
   DeviceGuard dg(p->device);
   const size_t w = size_t(p->M + 1) * 4;
-  HIPCHK(hipMemcpy2DAsync(d_psi, w, p->psi, size_t(p->P) * 4, w, size_t(p->eta) * p->n, hipMemcpyDeviceToDevice,
+  HIPCHK(hipMemcpy2DAsync(d_psi, w, p->psi, size_t(p->PP) * 4, w, size_t(p->eta) * p->n, hipMemcpyDeviceToDevice,
                           static_cast<hipStream_t>(stream)));
   return SHS_OK;
 }
@@ -442,10 +657,11 @@ shs_status shs_shearlet_forward(const shs_plan* p, int32_t count, const float* d
   shs_status st = make_ctx(p, d_ws, ws_bytes, stream, c);
   if (st != SHS_OK) return st;
   enqueue_synthesis(c, d_f, count);
-  RowParams rp = row_params(c);
+  RowParams rp{};
   rp.spec_in = c.at<float2>(c.L.t1);
+  rp.lin = pruned_layout(p);
   rp.real_out = d_c;
-  c.ops.row(ROW_C2R, ST_F32, false, rp, count * p->eta, c.s);
+  run_row(c, ROW_C2R, ST_F32, false, rp, count * p->eta);
   LAUNCHCHK("forward");
   return SHS_OK;
 }
@@ -458,15 +674,17 @@ shs_status shs_shearlet_adjoint(const shs_plan* p, int32_t count, const float* d
   Ctx c;
   shs_status st = make_ctx(p, d_ws, ws_bytes, stream, c);
   if (st != SHS_OK) return st;
-  RowParams rp = row_params(c);
+  RowParams rp{};
   rp.real_in = d_c;
   rp.spec_out = c.at<float2>(c.L.t2);
-  c.ops.row(ROW_R2C, ST_F32, false, rp, count * p->eta, c.s);
+  rp.lout = pruned_layout(p);
+  run_row(c, ROW_R2C, ST_F32, false, rp, count * p->eta);
   enqueue_analysis(c, count);
-  RowParams rz = row_params(c);
+  RowParams rz{};
   rz.spec_in = c.at<float2>(c.L.z);
+  rz.lin = dense_layout(p);
   rz.real_out = d_f;
-  c.ops.row(ROW_C2R, ST_F32, false, rz, count, c.s);
+  run_row(c, ROW_C2R, ST_F32, false, rz, count);
   LAUNCHCHK("adjoint");
   return SHS_OK;
 }
@@ -504,16 +722,18 @@ shs_status shs_solve(const shs_plan* p, const shs_params* prm, const float* d_s,
   const Layout& L = c.L;
   float* W = c.at<float>(L.w);
   float* BW = c.at<float>(L.bw);
+  const SpecLayout pl = pruned_layout(p);
 
   if (!prm->resume) {
     HIPCHK(hipMemsetAsync(c.ws + L.g, 0, L.w - L.g, c.s));
     HIPCHK(hipMemsetAsync(W, 0, size_t(q) * n2 * 4, c.s));
     HIPCHK(hipMemsetAsync(BW, 0, size_t(q) * n2 * 4, c.s));
   } else {
-    RowParams rp = row_params(c);
+    RowParams rp{};
     rp.g = c.ws + L.g;
     rp.spec_out = c.at<float2>(L.t2);
-    c.ops.row(ROW_PRIME, p->store, false, rp, q * eta, c.s);
+    rp.lout = pl;
+    run_row(c, ROW_PRIME, p->store, false, rp, q * eta);
     LAUNCHCHK("prime");
   }
 
@@ -529,10 +749,11 @@ shs_status shs_solve(const shs_plan* p, const shs_params* prm, const float* d_s,
     // ---- u-update: z = S^T (v - b_v) per label
     if (have_adjoint_input) {
       enqueue_analysis(c, q);
-      RowParams rz = row_params(c);
+      RowParams rz{};
       rz.spec_in = c.at<float2>(L.z);
+      rz.lin = dense_layout(p);
       rz.real_out = c.at<float>(L.zs);
-      c.ops.row(ROW_C2R, ST_F32, false, rz, q, c.s);
+      run_row(c, ROW_C2R, ST_F32, false, rz, q);
     }
     PixParams pp{};
     pp.z = c.at<float>(L.zs);
@@ -544,21 +765,27 @@ shs_status shs_solve(const shs_plan* p, const shs_params* prm, const float* d_s,
     pp.n2 = n2;
     pp.gamma = prm->gamma;
     pp.q = q;
-    if (have_adjoint_input) {
-      if (stats) hipLaunchKernelGGL((k_pixel<true, true>), dim3(unsigned(npix_blocks)), dim3(256), 0, c.s, pp);
-      else hipLaunchKernelGGL((k_pixel<false, true>), dim3(unsigned(npix_blocks)), dim3(256), 0, c.s, pp);
-    } else {
-      if (stats) hipLaunchKernelGGL((k_pixel<true, false>), dim3(unsigned(npix_blocks)), dim3(256), 0, c.s, pp);
-      else hipLaunchKernelGGL((k_pixel<false, false>), dim3(unsigned(npix_blocks)), dim3(256), 0, c.s, pp);
+    {
+      Timed tm(c.s, KC_PIXEL);
+      const dim3 g{unsigned(npix_blocks)}, b{256};
+      if (have_adjoint_input) {
+        if (stats) hipLaunchKernelGGL((k_pixel<true, true>), g, b, 0, c.s, pp);
+        else hipLaunchKernelGGL((k_pixel<false, true>), g, b, 0, c.s, pp);
+      } else {
+        if (stats) hipLaunchKernelGGL((k_pixel<true, false>), g, b, 0, c.s, pp);
+        else hipLaunchKernelGGL((k_pixel<false, false>), g, b, 0, c.s, pp);
+      }
     }
     // ---- v-update and b_v-update with S u, fused with the next adjoint's row FFT
     enqueue_synthesis(c, c.at<float>(L.us), q);
-    RowParams rp = row_params(c);
+    RowParams rp{};
     rp.spec_in = c.at<float2>(L.t1);
+    rp.lin = pl;
     rp.spec_out = c.at<float2>(L.t2);
+    rp.lout = pl;
     rp.g = c.ws + L.g;
     rp.emit = last ? 0 : 1;
-    c.ops.row(ROW_SOLVE, p->store, stats, rp, q * eta, c.s);
+    run_row(c, ROW_SOLVE, p->store, stats, rp, q * eta);
     LAUNCHCHK("iteration");
     have_adjoint_input = true;
     if (stats) {
@@ -575,6 +802,7 @@ shs_status shs_solve(const shs_plan* p, const shs_params* prm, const float* d_s,
     }
   }
   if (d_u || d_labels) {
+    Timed tm(c.s, KC_OTHER);
     hipLaunchKernelGGL(k_epilogue, dim3(unsigned(npix_blocks)), dim3(256), 0, c.s, W, q, n2, d_u, d_labels);
     LAUNCHCHK("epilogue");
   }
