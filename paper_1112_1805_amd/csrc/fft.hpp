@@ -130,6 +130,15 @@ __device__ __forceinline__ void RegDFT<R, INV>::run(cpx (&a)[R]) {
     cpx t = a[0];
     a[0] = t + a[1];
     a[1] = t - a[1];
+  } else if constexpr (R == 3) {
+    // X0 = a0 + s, X1,2 = a0 - s/2 -+ i (sqrt(3)/2) d  (forward), s = a1 + a2, d = a1 - a2
+    constexpr float h = 0.86602540378443864676f;
+    const cpx s = a[1] + a[2], d = a[1] - a[2];
+    const cpx t = cpx{a[0].x - 0.5f * s.x, a[0].y - 0.5f * s.y};
+    const cpx r = INV ? mul_i(d * h) : mul_mi(d * h);
+    a[0] = a[0] + s;
+    a[1] = t + r;
+    a[2] = t - r;
   } else if constexpr (R == 4) {
     cpx s0 = a[0] + a[2], d0 = a[0] - a[2];
     cpx s1 = a[1] + a[3], d1 = a[1] - a[3];

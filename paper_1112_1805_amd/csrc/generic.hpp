@@ -1,0 +1,364 @@
+// Row and column passes for image sizes that are not a power of two (N = 2^a * m with
+// m's prime factors in {3, 5, 7, 11, 13, 17, 19, 23}), e.g. the 32 * {3..24} sizes of a
+// batch of mixed images.  The data of a transform stays in LDS between stages; every stage
+// of the mixed-radix Stockham FFT has a runtime radix from a small set, each with a
+// compile-time butterfly: power-of-two radices use the register DFTs of fft.hpp, radix 9 a
+// 3 x 3 split, odd primes the symmetric-pair form
+//   X[k]   = a0 + sum_n (a_n + a_{P-n}) cos(2 pi n k/P) - i (a_n - a_{P-n}) sin(2 pi n k/P)
+//   X[P-k] = a0 + sum_n (a_n + a_{P-n}) cos(2 pi n k/P) + i (a_n - a_{P-n}) sin(2 pi n k/P)
+// (forward; the inverse swaps the signs of the sine terms).
+#pragma once
+#include "kernels.hpp"
+
+namespace shs {
+
+constexpr int kMaxStages = 10;
+struct FftPlan {
+  int L;                     // transform length
+  int ns;                    // number of stages
+  int radix[kMaxStages];     // product = L
+};
+
+// ---------------------------------------------------------------- small DFTs
+template <int P, bool INV>
+__device__ __forceinline__ void dft_odd_prime(cpx (&a)[P]) {
+  constexpr int H = (P - 1) / 2;
+  cpx s[H], d[H];
+  cpx sum = a[0];
+  static_for<H>([&](auto i) {
+    s[i] = a[i + 1] + a[P - 1 - i];
+    d[i] = a[i + 1] - a[P - 1 - i];
+    sum = sum + s[i];
+  });
+  const cpx a0 = a[0];
+  a[0] = sum;
+  static_for<H>([&](auto kk) {
+    constexpr int k = kk + 1;
+    cpx re = a0, im = cpx{0.f, 0.f};
+    static_for<H>([&](auto i) {
+      constexpr int n = i + 1;
+      constexpr float c = float(cos2pi(n * k, P));
+      constexpr float sn = float(sin2pi(n * k, P));
+      re = cpx{fmaf(s[i].x, c, re.x), fmaf(s[i].y, c, re.y)};
+      im = cpx{fmaf(d[i].x, sn, im.x), fmaf(d[i].y, sn, im.y)};
+    });
+    // forward: X[k] = re - i im, X[P-k] = re + i im
+    const cpx t = INV ? mul_i(im) : mul_mi(im);
+    a[k] = re + t;
+    a[P - k] = re - t;
+  });
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft_any(cpx (&a)[R]) {
+  if constexpr (R == 2 || R == 4 || R == 8 || R == 16) {
+    RegDFT<R, INV>::run(a);
+  } else if constexpr (R == 9) {
+    reg_dft_split<9, 3, 3, INV>(a);
+  } else {
+    dft_odd_prime<R, INV>(a);
+  }
+}
+
+// ---------------------------------------------------------------- one Stockham stage
+// `items` = W interleaved transforms x (L / R) butterflies, spread over nthr threads.
+// Element `pos` of transform c lives at buf[pos * W + c].  tw: exp(-2 pi i m / (L*twstep)).
+template <int R, bool INV>
+__device__ __forceinline__ void gstage(const float2* __restrict__ src, float2* __restrict__ dst, int L, int Ns, int W,
+                                       int nthr, int tid, const float2* __restrict__ tw, int twstep) {
+  const int nb = L / R;
+  const int items = nb * W;
+  const int tws = (L / (Ns * R)) * twstep;
+  for (int it = tid; it < items; it += nthr) {
+    const int c = it % W, bf = it / W;
+    const int k = bf % Ns;
+    cpx a[R];
+    static_for<R>([&](auto i) { a[i] = ld(src + (bf + i * nb) * W + c); });
+    if (Ns > 1) {
+      static_for<R - 1>([&](auto i1) {
+        constexpr int i = i1 + 1;
+        const cpx w = ld(tw + (i * k) * tws);
+        a[i] = INV ? cmulc(a[i], w) : cmul(a[i], w);
+      });
+    }
+    dft_any<R, INV>(a);
+    const int ob = (bf / Ns) * Ns * R + k;
+    static_for<R>([&](auto i) { st(dst + (ob + i * Ns) * W + c, a[i]); });
+  }
+}
+
+// Full transform: data in b0 (natural order) -> result (natural order) in the returned buffer.
+template <bool INV, int SK>
+__device__ float2* gfft(float2* b0, float2* b1, const FftPlan& pl, int W, int nthr, int tid,
+                        const float2* __restrict__ tw, int twstep) {
+  float2* src = b0;
+  float2* dst = b1;
+  int Ns = 1;
+  for (int s = 0; s < pl.ns; ++s) {
+    const int r = pl.radix[s];
+    switch (r) {
+      case 2: gstage<2, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
+      case 3: gstage<3, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
+      case 4: gstage<4, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
+      case 5: gstage<5, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
+      case 7: gstage<7, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
+      case 8: gstage<8, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
+      case 9: gstage<9, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
+      case 11: gstage<11, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
+      case 13: gstage<13, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
+      case 16: gstage<16, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
+      case 17: gstage<17, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
+      case 19: gstage<19, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
+      case 23: gstage<23, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
+      default: break;
+    }
+    fft_sync<SK>();
+    float2* t = src;
+    src = dst;
+    dst = t;
+    Ns *= r;
+  }
+  return src;
+}
+
+// ---------------------------------------------------------------- generic geometry
+constexpr int kGW = 4;          // strip width of the generic path
+constexpr int kGRows = 4;       // rows per block (one row per wave)
+
+__device__ __forceinline__ long long tix_rt(int ip, int row, int n) {
+  return (long long)(ip / kGW) * (n * kGW) + row * kGW + (ip % kGW);
+}
+
+struct GenParams {
+  FftPlan prow;   // length N/2
+  FftPlan pcol;   // length N
+  int n;
+};
+
+// ---------------------------------------------------------------- generic row pass
+// Same modes and data contract as k_row; one row per wave, the row's two half-length
+// complex transforms live in LDS (2 x N/2 bins per wave, dynamic shared memory).
+template <int MODE, int ST, bool STATS>
+__global__ __launch_bounds__(256) void k_row_g(RowParams p, GenParams gp) {
+  using S = Store<ST>;
+  extern __shared__ float2 gsm[];
+  __shared__ double red[4 * 4];
+  const int n = gp.n, M = n / 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = blockIdx.x * kGRows + wave;
+  const int ch = blockIdx.y;
+  const int j = ch % p.eta;
+  float2* b0 = gsm + wave * 2 * M;
+  float2* b1 = b0 + M;
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  float2* res = b0;
+
+  if constexpr (MODE == ROW_SOLVE || MODE == ROW_C2R || MODE == ROW_ENERGY) {
+    int cb, pitch;
+    long long off;
+    plane_geom(p.lin, ch % p.lin.nf, cb, pitch, off);
+    const float2* X = p.spec_in + (ch / p.lin.nf) * p.lin.ls + off;
+    for (int k = lane; k < M; k += 64) {
+      const unsigned ip = unsigned(k - cb), im = unsigned(M - k - cb);
+      const cpx xp = ip < unsigned(pitch) ? ld(X + tix_rt(int(ip), row, n)) : cpx{0.f, 0.f};
+      const cpx xm = im < unsigned(pitch) ? conj(ld(X + tix_rt(int(im), row, n))) : cpx{0.f, 0.f};
+      const cpx s = xp + xm, d = xp - xm;
+      const cpx w = conj(ld(p.tw + k));
+      st(b0 + k, s + mul_i(cmul(d, w)));
+    }
+    fft_sync<SYNC_WAVE>();
+    res = gfft<true, SYNC_WAVE>(b0, b1, gp.prow, 1, 64, lane, p.tw, 2);
+  }
+  if constexpr (MODE == ROW_C2R) {
+    float* out = p.real_out + ch * p.real_cs + (long long)row * n;
+    for (int k = lane; k < M; k += 64) {
+      const float2 v = res[k];
+      *reinterpret_cast<float2*>(out + 2 * k) = v;
+    }
+    return;
+  }
+  if constexpr (MODE == ROW_ENERGY) {
+    for (int k = lane; k < M; k += 64) acc[SLOT_L1] += fabsf(res[k].x) + fabsf(res[k].y);
+  }
+  if constexpr (MODE == ROW_R2C) {
+    const float* in = p.real_in + ch * p.real_cs + (long long)row * n;
+    for (int k = lane; k < M; k += 64) res[k] = *reinterpret_cast<const float2*>(in + 2 * k);
+  }
+  if constexpr (MODE == ROW_SOLVE || MODE == ROW_PRIME) {
+    typename S::T* g = reinterpret_cast<typename S::T*>(p.g) + (long long)ch * n * n + (long long)row * n;
+    const float th = p.fw.thr[j];
+    for (int k = lane; k < M; k += 64) {
+      float g0, g1;
+      S::unpack(S::load_pair(g + 2 * k), g0, g1);
+      const float b0v = fminf(fmaxf(g0, -th), th), b1v = fminf(fmaxf(g1, -th), th);
+      float n0 = g0, n1 = g1;
+      if constexpr (MODE == ROW_SOLVE) {
+        const float2 c = res[k];
+        n0 = S::round(b0v + c.x);
+        n1 = S::round(b1v + c.y);
+        S::store2(g + 2 * k, n0, n1);
+      }
+      const float nb0 = fminf(fmaxf(n0, -th), th), nb1 = fminf(fmaxf(n1, -th), th);
+      if constexpr (STATS && MODE == ROW_SOLVE) {
+        const float dv0 = (n0 - nb0) - (g0 - b0v), dv1 = (n1 - nb1) - (g1 - b1v);
+        const float db0 = nb0 - b0v, db1 = nb1 - b1v;
+        acc[SLOT_DY2] += dv0 * dv0 + dv1 * dv1;
+        acc[SLOT_DB2] += db0 * db0 + db1 * db1;
+        acc[SLOT_L1] += fabsf(n0 - nb0) + fabsf(n1 - nb1);
+      }
+      res[k] = make_float2(n0 - 2.f * nb0, n1 - 2.f * nb1);
+    }
+  }
+  if constexpr (MODE == ROW_R2C || MODE == ROW_PRIME || MODE == ROW_SOLVE) {
+    bool emit = true;
+    if constexpr (MODE == ROW_SOLVE) emit = p.emit != 0;
+    if (emit) {
+      fft_sync<SYNC_WAVE>();
+      float2* other = res == b0 ? b1 : b0;
+      float2* Y = gfft<false, SYNC_WAVE>(res, other, gp.prow, 1, 64, lane, p.tw, 2);
+      int cb, pitch;
+      long long off;
+      plane_geom(p.lout, ch % p.lout.nf, cb, pitch, off);
+      float2* X = p.spec_out + (ch / p.lout.nf) * p.lout.ls + off;
+      for (int k = lane; k <= M; k += 64) {
+        const unsigned ip = unsigned(k - cb);
+        if (ip < unsigned(pitch)) {
+          const cpx yk = ld(Y + (k == M ? 0 : k));
+          const cpx ym = conj(ld(Y + (k == 0 ? 0 : M - k)));
+          const cpx s = yk + ym, d = yk - ym;
+          const cpx w = ld(p.tw + k);
+          st(X + tix_rt(int(ip), row, n), (s - mul_i(cmul(d, w))) * 0.5f);
+        }
+      }
+    }
+  }
+  if constexpr (STATS) {
+    double dd[4] = {double(acc[0]), double(acc[1]), double(acc[2]), double(acc[3])};
+    dd[SLOT_L1] *= double(p.fw.lam[j]);
+    block_sum4<4>(dd, red);
+    if (threadIdx.x == 0) {
+      double* o = p.partials + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * 4;
+      o[0] = dd[0]; o[1] = dd[1]; o[2] = dd[2]; o[3] = dd[3];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- generic column passes
+// One strip (kGW columns) per block of 256 threads; a strip's N x kGW bins are one
+// contiguous block in memory and in LDS (bin (k0, c) at k0 * kGW + c).
+__device__ __forceinline__ float psi_at_rt(const ColParams& p, int4 win, int k0, int n) {
+  int rel = k0 - win.x;
+  if (rel < 0) rel += n;
+  return rel < win.y ? p.psiw[win.z + rel] : 0.f;
+}
+
+__global__ __launch_bounds__(256) void k_colg_fwd(ColParams p, GenParams gp) {
+  extern __shared__ float2 gsm[];
+  const int n = gp.n, E = n * kGW;
+  float2* b0 = gsm;
+  float2* b1 = gsm + E;
+  const long long strip = blockIdx.y * (long long)n * p.P + (long long)blockIdx.x * E;
+  for (int e = threadIdx.x; e < E; e += 256) b0[e] = p.in[strip + e];
+  __syncthreads();
+  float2* r = gfft<false, SYNC_BLOCK>(b0, b1, gp.pcol, kGW, 256, threadIdx.x, p.tw, 1);
+  const int M = n / 2;
+  for (int e = threadIdx.x; e < E; e += 256)
+    if (blockIdx.x * kGW + (e % kGW) <= M) p.out[strip + e] = r[e];
+}
+
+__global__ __launch_bounds__(256) void k_colg_syn(ColParams p, GenParams gp) {
+  extern __shared__ float2 gsm[];
+  const int n = gp.n, E = n * kGW, M = n / 2;
+  float2* bu = gsm;
+  float2* b0 = gsm + E;
+  float2* b1 = gsm + 2 * E;
+  const int4 it = p.items[blockIdx.x];
+  const int l = blockIdx.y;
+  const float2* U = p.in + l * (long long)n * p.P + (long long)it.x * E;
+  for (int e = threadIdx.x; e < E; e += 256) bu[e] = U[e];
+  __syncthreads();
+  for (int i = 0; i < it.z; ++i) {
+    const int j = p.flist[it.y + i];
+    for (int e = threadIdx.x; e < E; e += 256) {
+      const int c = e % kGW, k0 = e / kGW, k1 = it.x * kGW + c;
+      float f = 0.f;
+      if (k1 <= M) f = psi_at_rt(p, p.pwin[j * (M + 1) + k1], k0, n);
+      b0[e] = make_float2(bu[e].x * f * p.inv_n2, bu[e].y * f * p.inv_n2);
+    }
+    __syncthreads();
+    float2* r = gfft<true, SYNC_BLOCK>(b0, b1, gp.pcol, kGW, 256, threadIdx.x, p.tw, 1);
+    int cb, pitch;
+    long long off;
+    plane_geom(p.tl, j, cb, pitch, off);
+    float2* o = p.out + l * p.tl.ls + off + (long long)(it.x - cb / kGW) * E;
+    for (int e = threadIdx.x; e < E; e += 256)
+      if (it.x * kGW + (e % kGW) <= M) o[e] = r[e];
+    __syncthreads();
+  }
+}
+
+__device__ void colg_finish(const ColParams& p, const GenParams& gp, float2* acc, float2* b1, int strip, int l) {
+  const int n = gp.n, E = n * kGW, M = n / 2;
+  for (int e = threadIdx.x; e < E; e += 256) acc[e] = make_float2(acc[e].x * p.inv_n2, acc[e].y * p.inv_n2);
+  __syncthreads();
+  float2* r = gfft<true, SYNC_BLOCK>(acc, b1, gp.pcol, kGW, 256, threadIdx.x, p.tw, 1);
+  float2* o = p.out + l * (long long)n * p.P + (long long)strip * E;
+  for (int e = threadIdx.x; e < E; e += 256)
+    if (strip * kGW + (e % kGW) <= M) o[e] = r[e];
+}
+
+__global__ __launch_bounds__(256) void k_colg_ana(ColParams p, GenParams gp) {
+  extern __shared__ float2 gsm[];
+  const int n = gp.n, E = n * kGW, M = n / 2;
+  float2* ba = gsm;
+  float2* b0 = gsm + E;
+  float2* b1 = gsm + 2 * E;
+  const int4 it = p.items[blockIdx.x];
+  const int l = blockIdx.y;
+  for (int e = threadIdx.x; e < E; e += 256) ba[e] = make_float2(0.f, 0.f);
+  for (int i = 0; i < it.z; ++i) {
+    const int j = p.flist[it.y + i];
+    int cb, pitch;
+    long long off;
+    plane_geom(p.tl, j, cb, pitch, off);
+    const float2* in = p.in + l * p.tl.ls + off + (long long)(it.x - cb / kGW) * E;
+    for (int e = threadIdx.x; e < E; e += 256) {
+      const int k1 = it.x * kGW + (e % kGW);
+      b0[e] = k1 <= M ? in[e] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    float2* r = gfft<false, SYNC_BLOCK>(b0, b1, gp.pcol, kGW, 256, threadIdx.x, p.tw, 1);
+    for (int e = threadIdx.x; e < E; e += 256) {
+      const int c = e % kGW, k0 = e / kGW, k1 = it.x * kGW + c;
+      float f = 0.f;
+      if (k1 <= M) f = psi_at_rt(p, p.pwin[j * (M + 1) + k1], k0, n);
+      ba[e] = make_float2(ba[e].x + r[e].x * f, ba[e].y + r[e].y * f);
+    }
+    __syncthreads();
+  }
+  if (it.w < 0) {
+    colg_finish(p, gp, ba, b1, it.x, l);
+  } else {
+    float2* o = p.part + ((long long)it.w * p.labels + l) * E;
+    for (int e = threadIdx.x; e < E; e += 256) o[e] = ba[e];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_colg_final(ColParams p, GenParams gp) {
+  extern __shared__ float2 gsm[];
+  const int n = gp.n, E = n * kGW;
+  const int2 si = p.strips[blockIdx.x];
+  if (si.y <= 1) return;
+  float2* ba = gsm;
+  float2* b1 = gsm + E;
+  const int l = blockIdx.y;
+  for (int e = threadIdx.x; e < E; e += 256) ba[e] = make_float2(0.f, 0.f);
+  for (int i = 0; i < si.y; ++i) {
+    const float2* in = p.part + ((long long)p.items[si.x + i].w * p.labels + l) * E;
+    for (int e = threadIdx.x; e < E; e += 256) ba[e] = make_float2(ba[e].x + in[e].x, ba[e].y + in[e].y);
+  }
+  __syncthreads();
+  colg_finish(p, gp, ba, b1, blockIdx.x, l);
+}
+
+}  // namespace shs

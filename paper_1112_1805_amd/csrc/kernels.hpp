@@ -627,7 +627,7 @@ __global__ void k_filter_compact(const float* __restrict__ psi, int n, int P, in
     const int j = i / half, k1 = i % half;
     const int4 w = pwin[i];
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < w.y; r += gridDim.x * blockDim.x)
-      psiw[w.z + r] = psi[((long long)j * n + ((w.x + r) & (n - 1))) * P + k1];
+      psiw[w.z + r] = psi[((long long)j * n + ((w.x + r) % n)) * P + k1];
   }
 }
 

@@ -14,11 +14,15 @@
 
 #include "shearseg.h"
 #include "kernels.hpp"
+#include "generic.hpp"
 
 using namespace shs;
 
 struct shs_plan {
   int n, C, q, J, store, eta, M, P, PP, W, NS, device;
+  int generic;         // 1: mixed-radix path (N not a power of two)
+  int rpb;             // rows per row-pass block
+  FftPlan prow, pcol;  // mixed-radix stage lists (generic path)
   float* psi;          // [eta][N][PP] dense filter bank (half spectrum)
   float2* tw;          // [N] exp(-2 pi i m / N)
   // pruned layout
@@ -158,7 +162,7 @@ Layout make_layout(const shs_plan* p) {
   L.zs = off;  off = align256(off + q * nn * 4);
   L.us = off;  off = align256(off + q * nn * 4);
   L.part = off; off = align256(off + size_t(std::max(p->n_part, 1)) * q * n * p->W * 8);
-  L.nrow_parts = (long long)(q * eta) * (n / by_size<RpbOf>(p->n));
+  L.nrow_parts = (long long)(q * eta) * (n / p->rpb);
   const long long npix = (long long)((nn + 255) / 256);
   L.nparts = L.nrow_parts + std::max<long long>(npix, kDotBlocks);
   L.parts = off; off = align256(off + size_t(L.nparts) * 4 * 8);
@@ -179,7 +183,7 @@ struct Pipe {
     dim3 grid(N / RG::RPB, channels);
     hipLaunchKernelGGL((k_row<N, MODE, ST, STATS>), grid, dim3(256), 0, s, rp);
   }
-  static void row(int mode, int store, bool stats, const RowParams& rp, int channels, hipStream_t s) {
+  static void row(const shs_plan*, int mode, int store, bool stats, const RowParams& rp, int channels, hipStream_t s) {
     switch (mode) {
       case ROW_SOLVE:
         if (store == ST_F32) { stats ? row_t<ROW_SOLVE, ST_F32, true>(rp, channels, s) : row_t<ROW_SOLVE, ST_F32, false>(rp, channels, s); }
@@ -196,7 +200,7 @@ struct Pipe {
       case ROW_ENERGY: row_t<ROW_ENERGY, ST_F32, true>(rp, channels, s); break;
     }
   }
-  static void col(int kind, const ColParams& cp, int nblocks, int labels, hipStream_t s) {
+  static void col(const shs_plan*, int kind, const ColParams& cp, int nblocks, int labels, hipStream_t s) {
     const dim3 grid(nblocks, labels), block(CG::THREADS);
     switch (kind) {
       case 0: hipLaunchKernelGGL((k_col_fwd<N>), grid, block, 0, s, cp); break;
@@ -208,9 +212,48 @@ struct Pipe {
 };
 enum { COL_FWD = 0, COL_SYN = 1, COL_ANA = 2, COL_FINAL = 3 };
 
+// Mixed-radix (generic) launchers: runtime N, one row per wave, LDS-resident transforms.
+struct GenPipe {
+  static GenParams gp(const shs_plan* p) { return GenParams{p->prow, p->pcol, p->n}; }
+  template <int MODE, int ST, bool STATS>
+  static void row_t(const shs_plan* p, const RowParams& rp, int channels, hipStream_t s) {
+    const dim3 grid(p->n / kGRows, channels);
+    const size_t lds = size_t(kGRows) * 2 * p->M * sizeof(float2);
+    hipLaunchKernelGGL((k_row_g<MODE, ST, STATS>), grid, dim3(256), lds, s, rp, gp(p));
+  }
+  static void row(const shs_plan* p, int mode, int store, bool stats, const RowParams& rp, int channels,
+                  hipStream_t s) {
+    switch (mode) {
+      case ROW_SOLVE:
+        if (store == ST_F32) { stats ? row_t<ROW_SOLVE, ST_F32, true>(p, rp, channels, s) : row_t<ROW_SOLVE, ST_F32, false>(p, rp, channels, s); }
+        else if (store == ST_BF16) { stats ? row_t<ROW_SOLVE, ST_BF16, true>(p, rp, channels, s) : row_t<ROW_SOLVE, ST_BF16, false>(p, rp, channels, s); }
+        else { stats ? row_t<ROW_SOLVE, ST_F16, true>(p, rp, channels, s) : row_t<ROW_SOLVE, ST_F16, false>(p, rp, channels, s); }
+        break;
+      case ROW_PRIME:
+        if (store == ST_F32) row_t<ROW_PRIME, ST_F32, false>(p, rp, channels, s);
+        else if (store == ST_BF16) row_t<ROW_PRIME, ST_BF16, false>(p, rp, channels, s);
+        else row_t<ROW_PRIME, ST_F16, false>(p, rp, channels, s);
+        break;
+      case ROW_C2R: row_t<ROW_C2R, ST_F32, false>(p, rp, channels, s); break;
+      case ROW_R2C: row_t<ROW_R2C, ST_F32, false>(p, rp, channels, s); break;
+      case ROW_ENERGY: row_t<ROW_ENERGY, ST_F32, true>(p, rp, channels, s); break;
+    }
+  }
+  static void col(const shs_plan* p, int kind, const ColParams& cp, int nblocks, int labels, hipStream_t s) {
+    const dim3 grid(nblocks, labels), block(256);
+    const size_t e = size_t(p->n) * kGW * sizeof(float2);
+    switch (kind) {
+      case 0: hipLaunchKernelGGL(k_colg_fwd, grid, block, 2 * e, s, cp, gp(p)); break;
+      case 1: hipLaunchKernelGGL(k_colg_syn, grid, block, 3 * e, s, cp, gp(p)); break;
+      case 2: hipLaunchKernelGGL(k_colg_ana, grid, block, 3 * e, s, cp, gp(p)); break;
+      case 3: hipLaunchKernelGGL(k_colg_final, grid, block, 2 * e, s, cp, gp(p)); break;
+    }
+  }
+};
+
 struct Ops {
-  void (*row)(int, int, bool, const RowParams&, int, hipStream_t);
-  void (*col)(int, const ColParams&, int, int, hipStream_t);
+  void (*row)(const shs_plan*, int, int, bool, const RowParams&, int, hipStream_t);
+  void (*col)(const shs_plan*, int, const ColParams&, int, int, hipStream_t);
 };
 
 template <int N>
@@ -218,7 +261,32 @@ Ops ops_for() {
   return Ops{&Pipe<N>::row, &Pipe<N>::col};
 }
 
-bool get_ops(int n, Ops& o) {
+// Stage list of a mixed-radix transform of length L (radices 16, 8, 4, 2, 9, 3 and the
+// primes 5..23); false if L has a larger prime factor.
+bool make_fft_plan(int L, FftPlan& pl) {
+  pl = FftPlan{};
+  pl.L = L;
+  int m = L;
+  std::vector<int> rs;
+  for (int pr : {23, 19, 17, 13, 11, 7, 5}) while (m % pr == 0) { rs.push_back(pr); m /= pr; }
+  while (m % 9 == 0) { rs.push_back(9); m /= 9; }
+  while (m % 3 == 0) { rs.push_back(3); m /= 3; }
+  while (m % 16 == 0) { rs.insert(rs.begin(), 16); m /= 16; }
+  if (m == 2 || m == 4 || m == 8) { rs.insert(rs.begin(), m); m = 1; }
+  if (m != 1 || int(rs.size()) > kMaxStages) return false;
+  pl.ns = int(rs.size());
+  for (int i = 0; i < pl.ns; ++i) pl.radix[i] = rs[i];
+  return true;
+}
+
+bool get_ops_pow2(int n, Ops& o);
+
+bool get_ops(const shs_plan* p, Ops& o) {
+  if (p->generic) { o = Ops{&GenPipe::row, &GenPipe::col}; return true; }
+  return get_ops_pow2(p->n, o);
+}
+
+bool get_ops_pow2(int n, Ops& o) {
   switch (n) {
     case 64: o = ops_for<64>(); return true;
     case 128: o = ops_for<128>(); return true;
@@ -256,7 +324,7 @@ shs_status make_ctx(const shs_plan* p, void* ws, size_t ws_bytes, void* stream, 
   if (!p) return fail(SHS_E_INVALID, "null plan");
   c.p = p;
   c.L = make_layout(p);
-  if (!get_ops(p->n, c.ops)) return fail(SHS_E_UNSUPPORTED, "unsupported size");
+  if (!get_ops(p, c.ops)) return fail(SHS_E_UNSUPPORTED, "unsupported size");
   if (!ws) return fail(SHS_E_WORKSPACE, "null workspace");
   if (ws_bytes < c.L.total)
     return fail(SHS_E_WORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes < required " +
@@ -278,7 +346,7 @@ void run_row(const Ctx& c, int mode, int store, bool stats, RowParams rp, int ch
   rp.fw = c.fw;
   rp.partials = c.at<double>(c.L.parts);
   Timed tm(c.s, row_class(mode));
-  c.ops.row(mode, store, stats, rp, channels, c.s);
+  c.ops.row(c.p, mode, store, stats, rp, channels, c.s);
 }
 
 ColParams col_params(const Ctx& c, int labels) {
@@ -301,7 +369,7 @@ ColParams col_params(const Ctx& c, int labels) {
 void run_col(const Ctx& c, int kind, const ColParams& cp, int nblocks, int labels) {
   static const int cls[4] = {KC_COL_FWD, KC_COL_SYN, KC_COL_ANA, KC_COL_FINAL};
   Timed tm(c.s, cls[kind]);
-  c.ops.col(kind, cp, nblocks, labels, c.s);
+  c.ops.col(c.p, kind, cp, nblocks, labels, c.s);
 }
 
 // S: real images [count][N][N] -> pruned coefficient spectra T1 (count * eta planes).
@@ -568,7 +636,14 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
     return fail(SHS_E_INVALID, "J must satisfy J >= 1 and 4^J <= 2N");
   if (shape->store < SHS_STORE_F32 || shape->store > SHS_STORE_F16) return fail(SHS_E_INVALID, "bad store type");
   Ops o;
-  if (!get_ops(n, o)) return fail(SHS_E_UNSUPPORTED, "n must be one of 64, 128, 256, 512, 1024, 2048");
+  FftPlan prow{}, pcol{};
+  const bool pow2 = get_ops_pow2(n, o);
+  if (!pow2) {
+    // mixed-radix path: N a multiple of 8 in [64, 1024] whose prime factors are <= 23
+    if (n % 8 != 0 || n < 64 || n > 1024 || !make_fft_plan(n / 2, prow) || !make_fft_plan(n, pcol))
+      return fail(SHS_E_UNSUPPORTED,
+                  "n must be a power of two in 64..2048 or a multiple of 8 in 64..1024 with prime factors <= 23");
+  }
   if (device < 0) return fail(SHS_E_INVALID, "bad device");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) return fail(SHS_E_DEVICE, "no such HIP device");
@@ -580,7 +655,11 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
   p->n = n; p->C = shape->channels; p->q = shape->q; p->J = shape->J; p->store = shape->store;
   p->eta = shs_num_filters(shape->J);
   p->M = n / 2;
-  p->W = by_size<WOf>(n);
+  p->generic = pow2 ? 0 : 1;
+  p->prow = prow;
+  p->pcol = pcol;
+  p->W = pow2 ? by_size<WOf>(n) : kGW;
+  p->rpb = pow2 ? by_size<RpbOf>(n) : kGRows;
   p->NS = p->M / p->W + 1;
   p->P = p->NS * p->W;  // columns of a dense spectrum plane (strip tiled); columns M+1.. unused
   p->PP = p->M + 16;    // row pitch of the dense filter bank
@@ -604,6 +683,17 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
   if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     free_plan(p);
     return fail(SHS_E_DEVICE, "filter generation failed");
+  }
+  if (p->generic) {
+    // generic column passes hold 3 strips of N x 4 bins in dynamic LDS (up to 96 KB)
+    const int lds3 = 3 * n * kGW * int(sizeof(float2));
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colg_syn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds3) != hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colg_ana), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds3) != hipSuccess) {
+      free_plan(p);
+      return fail(SHS_E_DEVICE, "cannot reserve LDS for the mixed-radix column passes");
+    }
   }
   const shs_status st = build_pruned_layout(p);
   if (st != SHS_OK) {

@@ -366,3 +366,50 @@ def test_energy_entry_point():
     e = plan.energy(s, dev_t(u), ws, w.lam)
     ref = O.energy(f32(u), f32(s.cpu().numpy()), O.filter_bank(128, 2), O.lambda_per_filter(w.lam, 2))
     assert abs(e - ref) / abs(ref) < 1e-6
+
+
+# ------------------------------------------------------------------ mixed-radix sizes
+# Image sides 32 * m (the sizes of a mixed batch) run the generic mixed-radix path.
+MIXED = [(96, 2, 1), (160, 3, 2), (224, 3, 1), (352, 3, 1), (480, 3, 2), (608, 3, 1), (736, 3, 1), (768, 3, 1)]
+
+
+@pytest.mark.parametrize("n,J,count", MIXED)
+def test_mixed_radix_transforms(n, J, count):
+    pkg = _pkg()
+    plan = pkg.Plan(n, 1, max(count, 2), J)
+    ws = plan.new_workspace()
+    f = random_image(n, seed=n + 7, channels=count).astype(np.float32)
+    c = torch.empty((count, plan.eta, n, n), dtype=torch.float32, device="cuda:0")
+    plan.shearlet_forward(dev_t(f), c, ws)
+    cd = random_data((count, plan.eta, n, n), seed=n * 5).astype(np.float32)
+    g = torch.empty((count, n, n), dtype=torch.float32, device="cuda:0")
+    plan.shearlet_adjoint(dev_t(cd), g, ws)
+    psi = torch.empty((plan.eta, n, n // 2 + 1), dtype=torch.float32, device="cuda:0")
+    plan.filters(psi)
+    torch.cuda.synchronize()
+    B = O.filter_bank(n, J)
+    assert np.max(np.abs(psi.cpu().numpy() - B[:, :, : n // 2 + 1])) < 1e-6
+    cg, gg = c.cpu().numpy(), g.cpu().numpy()
+    for i in range(count):
+        assert rel(cg[i], O.forward(f32(f[i]), B)) < 1e-5
+        assert rel(gg[i], O.adjoint(f32(cd[i]), B)) < 1e-5
+
+
+@pytest.mark.parametrize("n,q,J,C,iters", [(96, 3, 2, 1, 20), (160, 6, 3, 1, 12), (352, 2, 3, 3, 8),
+                                           (736, 4, 3, 1, 5)])
+def test_mixed_radix_solves(n, q, J, C, iters):
+    w = make_small(n, q, J, channels=C, seed=n + q, lam=0.1, iters=iters)
+    r, s, B, lam_f = run_oracle(w)
+    g = run_gpu(w)
+    assert np.max(np.abs(g["u"] - r.w)) < 2e-5
+    assert np.mean(g["labels"] == r.labels) >= 0.999
+    h = g["hist"]
+    assert np.max(np.abs(h[:, 2] - r.r_combined) / r.r_combined) < 1e-3
+
+
+def test_unsupported_sizes_rejected():
+    pkg = _pkg()
+    for n in (100, 62, 1056, 2 * 29 * 8):
+        with pytest.raises(pkg.ShsError) as e:
+            pkg.Plan(n, 1, 2, 2)
+        assert e.value.status == pkg.SHS_E_UNSUPPORTED
