@@ -160,6 +160,32 @@ shs_status shs_solve(const shs_plan* plan, const shs_params* params, const float
 shs_status shs_energy(const shs_plan* plan, const shs_params* params, const float* d_s, const float* d_u,
                       void* d_ws, size_t ws_bytes, double* h_energy, void* stream);
 
+/* ---- batches of images --------------------------------------------------------------
+ * A batch solves `count` independent problems of the model above (Section 3) whose images
+ * may differ in size N, label count q, channel count and storage type; each element of
+ * `shapes` follows the rules of shs_plan_create (one plan per distinct shape is created
+ * inside the batch).  Image i uses its own region of one workspace
+ * (shs_batch_workspace_bytes).
+ *
+ * shs_solve_batch runs params[i] on image i from the zero state (tol and resume are not
+ * supported: SHS_E_UNSUPPORTED; every image runs the same number of iterations).  The work
+ * of one ADMM iteration of all images is captured once into a HIP graph (images spread over
+ * internal streams so that small images run side by side) and the graphs are replayed on
+ * `stream`: one graph launch per iteration.  Graphs are re-captured whenever a pointer or
+ * parameter differs from the previous call.  The call returns without synchronising.
+ * d_s, d_u, d_labels: HOST arrays of `count` device pointers (d_u / d_labels and their
+ * entries may be NULL); layouts as in shs_solve.  d_stats: NULL or DEVICE float64
+ * [count][5] receiving, per image, the last iteration's |dy|^2, |db|^2, <w,s>,
+ * sum lambda|v| and a non-finite flag (1.0 if any of them is not finite).
+ * A batch object is not thread-safe (it owns its captured graphs). */
+typedef struct shs_batch shs_batch;
+shs_status shs_batch_create(int32_t count, const shs_shape* shapes, int device, shs_batch** out);
+shs_status shs_batch_destroy(shs_batch* batch);
+size_t shs_batch_workspace_bytes(const shs_batch* batch);
+shs_status shs_solve_batch(shs_batch* batch, const shs_params* params, const float* const* d_s, void* d_ws,
+                           size_t ws_bytes, float* const* d_u, int32_t* const* d_labels, double* d_stats,
+                           void* stream);
+
 /* ---- optional kernel timing (benchmarks) ------------------------------------------
  * Between shs_profile_begin() and shs_profile_end(), every kernel the library enqueues is
  * bracketed by a pair of HIP events recorded on the stream it is launched on.

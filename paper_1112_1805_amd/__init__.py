@@ -68,6 +68,11 @@ _SIGS = {
                          ctypes.POINTER(ShsStats), _VP]),
     "shs_energy": (_I32, [_VP, ctypes.POINTER(ShsParams), _VP, _VP, _VP, _SZ,
                           ctypes.POINTER(ctypes.c_double), _VP]),
+    "shs_batch_create": (_I32, [_I32, ctypes.POINTER(ShsShape), ctypes.c_int, ctypes.POINTER(_VP)]),
+    "shs_batch_destroy": (_I32, [_VP]),
+    "shs_batch_workspace_bytes": (_SZ, [_VP]),
+    "shs_solve_batch": (_I32, [_VP, ctypes.POINTER(ShsParams), ctypes.POINTER(_VP), _VP, _SZ,
+                               ctypes.POINTER(_VP), ctypes.POINTER(_VP), _VP, _VP]),
     "shs_profile_begin": (_I32, []),
     "shs_profile_end": (_I32, [ctypes.POINTER(ShsKernelTime), _I32]),
     "shs_status_str": (ctypes.c_char_p, [_I32]),
@@ -236,6 +241,58 @@ class Plan:
                                 ctypes.byref(e), _stream(stream)), "shs_energy")
         del keep
         return float(e.value)
+
+
+class Batch:
+    """Owns an shs_batch* : `count` images of different sizes / label counts solved together."""
+
+    def __init__(self, shapes, device=0):
+        """shapes: sequence of (n, channels, q, J, store)."""
+        arr = (ShsShape * len(shapes))(*[ShsShape(n, C, q, J, STORE_CODES[st] if isinstance(st, str) else int(st))
+                                          for n, C, q, J, st in shapes])
+        h = _VP()
+        _check(lib().shs_batch_create(len(shapes), arr, device, ctypes.byref(h)), "shs_batch_create")
+        self.handle = h
+        self.shapes = [tuple(x) for x in shapes]
+        self.count = len(shapes)
+        self.device = device
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.shs_batch_destroy(h)
+            self.handle = None
+
+    def workspace_bytes(self) -> int:
+        return int(lib().shs_batch_workspace_bytes(self.handle))
+
+    def new_workspace(self):
+        import torch
+        nb = self.workspace_bytes()
+        return torch.empty((nb + 255) // 256 * 256, dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def solve(self, s_list, ws, lams, gammas, iters, u_list=None, labels_list=None, stats=None, stream=None):
+        """shs_solve_batch.  s_list/u_list/labels_list: one device tensor per image; stats: None or
+        a float64 device tensor [count][5]."""
+        n = self.count
+        for i, (nn, C, q, J, st) in enumerate(self.shapes):
+            _expect(s_list[i], (q, nn, nn), "f32", f"d_s[{i}]")
+            if u_list is not None:
+                _expect(u_list[i], (q, nn, nn), "f32", f"d_u[{i}]")
+            if labels_list is not None:
+                _expect(labels_list[i], (nn, nn), "i32", f"d_labels[{i}]")
+        if stats is not None:
+            _expect(stats, (n, 5), "f64", "d_stats")
+        prm = (ShsParams * n)()
+        keep = []
+        for i in range(n):
+            p_i, arr = _params(lams[i], gammas[i], iters)
+            prm[i] = p_i
+            keep.append(arr)
+        ptrs = lambda ts: (_VP * n)(*[t.data_ptr() for t in ts]) if ts is not None else None
+        _check(lib().shs_solve_batch(self.handle, prm, ptrs(s_list), _ptr(ws), ws.numel(), ptrs(u_list),
+                                     ptrs(labels_list), _ptr(stats), _stream(stream)), "shs_solve_batch")
+        del keep
 
 
 def segment(img, codebook, J, lam, gamma, iters, store="f32", p=2.0, device=0, hist=False):

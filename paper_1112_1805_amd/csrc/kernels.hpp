@@ -784,9 +784,13 @@ __global__ __launch_bounds__(256) void k_reduce2(const double* __restrict__ in, 
   }
 }
 
-__global__ void k_fill_f32(float* __restrict__ p, long long n, float v) {
+__global__ void k_fill_u32(uint32_t* __restrict__ p, long long n, uint32_t v) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+__global__ void k_copy_f64(const double* __restrict__ src, int n, double* __restrict__ dst) {
+  if (int(threadIdx.x) < n) dst[threadIdx.x] = src[threadIdx.x];
 }
 
 }  // namespace shs

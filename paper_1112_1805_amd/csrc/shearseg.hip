@@ -79,10 +79,11 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // ---------------------------------------------------------------- kernel timing
 enum KClass {
   KC_ROW_SOLVE, KC_COL_SYN, KC_COL_ANA, KC_COL_FINAL, KC_COL_FWD, KC_ROW_C2R, KC_ROW_R2C, KC_ROW_PRIME,
-  KC_ROW_ENERGY, KC_PIXEL, KC_REDUCE, KC_OTHER, KC_COUNT
+  KC_ROW_ENERGY, KC_PIXEL, KC_REDUCE, KC_OTHER, KC_BATCH, KC_COUNT
 };
 const char* const kKClassName[KC_COUNT] = {"row_solve", "col_syn", "col_ana", "col_final", "col_fwd", "row_c2r",
-                                           "row_r2c", "row_prime", "row_energy", "pixel", "reduce", "other"};
+                                           "row_r2c", "row_prime", "row_energy", "pixel", "reduce", "other",
+                                           "batch_solve"};
 
 struct Prof {
   std::mutex mu;
@@ -95,6 +96,12 @@ Prof& prof() {
   static Prof p;
   return p;
 }
+// Set while a batch graph is being captured: no timing events inside graphs.
+thread_local int g_capturing = 0;
+struct CaptureScope {
+  CaptureScope() { ++g_capturing; }
+  ~CaptureScope() { --g_capturing; }
+};
 
 // Brackets the launches made during its lifetime with HIP events on stream s (when on).
 struct Timed {
@@ -102,7 +109,7 @@ struct Timed {
   hipEvent_t stop = nullptr;
   Timed(hipStream_t s_, int cls) : s(s_) {
     Prof& P = prof();
-    if (!P.on) return;
+    if (!P.on || g_capturing) return;
     std::lock_guard<std::mutex> g(P.mu);
     while (P.pool.size() < P.used + 2) {
       hipEvent_t e;
@@ -565,6 +572,131 @@ shs_status build_pruned_layout(shs_plan* p) {
   return SHS_OK;
 }
 
+
+shs_status check_params(const shs_params* prm) {
+  if (!(prm->gamma > 0.f) || !std::isfinite(prm->gamma)) return fail(SHS_E_INVALID, "gamma must be > 0");
+  if (prm->iters < 0) return fail(SHS_E_INVALID, "iters must be >= 0");
+  if (prm->tol < 0.0 || (prm->tol > 0.0 && prm->check_every < 1)) return fail(SHS_E_INVALID, "bad tol/check_every");
+  return SHS_OK;
+}
+
+// Zero ADMM state (v = w = b = 0) with a fill kernel, so that it can be captured in a graph.
+void enqueue_zero_state(const Ctx& c) {
+  const long long words = (long long)(c.L.state_end / 4);
+  hipLaunchKernelGGL(k_fill_u32, dim3(unsigned((words + 255) / 256)), dim3(256), 0, c.s,
+                     reinterpret_cast<uint32_t*>(c.ws + c.L.g), words, 0u);
+}
+
+void enqueue_epilogue(const Ctx& c, float* d_u, int32_t* d_labels) {
+  if (!d_u && !d_labels) return;
+  const long long n2 = (long long)c.p->n * c.p->n;
+  Timed tm(c.s, KC_OTHER);
+  hipLaunchKernelGGL(k_epilogue, dim3(unsigned((n2 + 255) / 256)), dim3(256), 0, c.s, c.at<float>(c.L.w), c.p->q, n2,
+                     d_u, d_labels);
+}
+
+// One ADMM iteration of one image (Section 3): u-update from the adjoint of the previous
+// iteration's (v - b_v) (absent on the first iteration), w/b_w update, forward transform,
+// v/b_v update fused with the next adjoint's row FFT (when `emit`), optional FP64 residual
+// reduction into `hist_row`.  Enqueues only; no host synchronisation.
+void enqueue_iteration(const Ctx& c, const float* d_s, float gamma, bool have_adjoint_input, bool stats, bool emit,
+                       double* hist_row) {
+  const shs_plan* p = c.p;
+  const Layout& L = c.L;
+  const int q = p->q;
+  const long long n2 = (long long)p->n * p->n;
+  const long long npix_blocks = (n2 + 255) / 256;
+  if (have_adjoint_input) {
+    enqueue_analysis(c, q);
+    RowParams rz{};
+    rz.spec_in = c.at<float2>(L.z);
+    rz.lin = dense_layout(p);
+    rz.real_out = c.at<float>(L.zs);
+    run_row(c, ROW_C2R, ST_F32, false, rz, q);
+  }
+  PixParams pp{};
+  pp.z = c.at<float>(L.zs);
+  pp.w = c.at<float>(L.w);
+  pp.bw = c.at<float>(L.bw);
+  pp.s = d_s;
+  pp.u = c.at<float>(L.us);
+  pp.partials = c.at<double>(L.parts) + L.nrow_parts * 4;
+  pp.n2 = n2;
+  pp.gamma = gamma;
+  pp.q = q;
+  {
+    Timed tm(c.s, KC_PIXEL);
+    const dim3 g{unsigned(npix_blocks)}, b{256};
+    if (have_adjoint_input) {
+      if (stats) hipLaunchKernelGGL((k_pixel<true, true>), g, b, 0, c.s, pp);
+      else hipLaunchKernelGGL((k_pixel<false, true>), g, b, 0, c.s, pp);
+    } else {
+      if (stats) hipLaunchKernelGGL((k_pixel<true, false>), g, b, 0, c.s, pp);
+      else hipLaunchKernelGGL((k_pixel<false, false>), g, b, 0, c.s, pp);
+    }
+  }
+  enqueue_synthesis(c, c.at<float>(L.us), q);
+  RowParams rp{};
+  rp.spec_in = c.at<float2>(L.t1);
+  rp.lin = pruned_layout(p);
+  rp.spec_out = c.at<float2>(L.t2);
+  rp.lout = pruned_layout(p);
+  rp.g = c.ws + L.g;
+  rp.emit = emit ? 1 : 0;
+  run_row(c, ROW_SOLVE, p->store, stats, rp, q * p->eta);
+  if (stats) enqueue_reduce(c, L.nrow_parts + npix_blocks, hist_row, gamma);
+}
+
+}  // namespace
+
+// A batch of images of different sizes and label counts (one plan per distinct shape).
+// Every iteration of all images is one captured graph (images forked over internal
+// streams so that small images run side by side), replayed on the caller's stream.
+struct shs_batch {
+  int count = 0, device = 0;
+  std::vector<shs_plan*> plans;
+  std::vector<int> plan_of;
+  std::vector<size_t> ws_off;
+  size_t ws_total = 0;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> join;
+  hipStream_t main = nullptr;
+  hipEvent_t fork = nullptr;
+  std::vector<double> key;
+  hipGraphExec_t g_init = nullptr, g_first = nullptr, g_mid = nullptr, g_last = nullptr;
+
+  void drop_graphs() {
+    for (hipGraphExec_t* g : {&g_init, &g_first, &g_mid, &g_last})
+      if (*g) { (void)hipGraphExecDestroy(*g); *g = nullptr; }
+    key.clear();
+  }
+  // Captures `body` (which enqueues on the internal streams) into an executable graph.
+  template <class F>
+  shs_status capture(F&& body, hipGraphExec_t* out) {
+    CaptureScope cs;
+    HIPCHK(hipStreamBeginCapture(main, hipStreamCaptureModeThreadLocal));
+    bool ok = hipEventRecord(fork, main) == hipSuccess;
+    for (hipStream_t s : streams) ok = ok && hipStreamWaitEvent(s, fork, 0) == hipSuccess;
+    if (ok) body();
+    ok = ok && hipGetLastError() == hipSuccess;
+    for (size_t k = 0; k < streams.size(); ++k) {
+      ok = ok && hipEventRecord(join[k], streams[k]) == hipSuccess;
+      ok = ok && hipStreamWaitEvent(main, join[k], 0) == hipSuccess;
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(main, &g);
+    if (!ok || e != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(SHS_E_DEVICE, "graph capture failed");
+    }
+    const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(SHS_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    return SHS_OK;
+  }
+};
+
+namespace {
 }  // namespace
 
 // ===================================================================== C ABI
@@ -796,36 +928,27 @@ shs_status shs_energy(const shs_plan* p, const shs_params* prm, const float* d_s
 shs_status shs_solve(const shs_plan* p, const shs_params* prm, const float* d_s, void* d_ws, size_t ws_bytes,
                      float* d_u, int32_t* d_labels, double* d_hist, shs_stats* h_stats, void* stream) {
   if (!p || !prm || !d_s) return fail(SHS_E_INVALID, "null argument");
-  if (!(prm->gamma > 0.f) || !std::isfinite(prm->gamma)) return fail(SHS_E_INVALID, "gamma must be > 0");
-  if (prm->iters < 0) return fail(SHS_E_INVALID, "iters must be >= 0");
-  if (prm->tol < 0.0 || (prm->tol > 0.0 && prm->check_every < 1)) return fail(SHS_E_INVALID, "bad tol/check_every");
+  shs_status st = check_params(prm);
+  if (st != SHS_OK) return st;
   DeviceGuard dg(p->device);
   Ctx c;
-  shs_status st = make_ctx(p, d_ws, ws_bytes, stream, c);
+  st = make_ctx(p, d_ws, ws_bytes, stream, c);
   if (st != SHS_OK) return st;
   st = set_lambda(c, prm);
   if (st != SHS_OK) return st;
 
-  const int q = p->q, eta = p->eta;
+  const int q = p->q;
   const long long n2 = (long long)p->n * p->n;
-  const long long npix_blocks = (n2 + 255) / 256;
-  const Layout& L = c.L;
-  float* W = c.at<float>(L.w);
-  float* BW = c.at<float>(L.bw);
-  const SpecLayout pl = pruned_layout(p);
-
   if (!prm->resume) {
-    HIPCHK(hipMemsetAsync(c.ws + L.g, 0, L.w - L.g, c.s));
-    HIPCHK(hipMemsetAsync(W, 0, size_t(q) * n2 * 4, c.s));
-    HIPCHK(hipMemsetAsync(BW, 0, size_t(q) * n2 * 4, c.s));
+    enqueue_zero_state(c);
   } else {
     RowParams rp{};
-    rp.g = c.ws + L.g;
-    rp.spec_out = c.at<float2>(L.t2);
-    rp.lout = pl;
-    run_row(c, ROW_PRIME, p->store, false, rp, q * eta);
-    LAUNCHCHK("prime");
+    rp.g = c.ws + c.L.g;
+    rp.spec_out = c.at<float2>(c.L.t2);
+    rp.lout = pruned_layout(p);
+    run_row(c, ROW_PRIME, p->store, false, rp, q * p->eta);
   }
+  LAUNCHCHK("initial state");
 
   const double rnorm = std::sqrt(double(q) * double(n2));
   int done = 0;
@@ -836,66 +959,20 @@ shs_status shs_solve(const shs_plan* p, const shs_params* prm, const float* d_s,
     const bool last = it == prm->iters - 1;
     const bool check = prm->tol > 0.0 && ((it + 1) % prm->check_every == 0 || last);
     const bool stats = d_hist != nullptr || check || (last && h_stats != nullptr);
-    // ---- u-update: z = S^T (v - b_v) per label
-    if (have_adjoint_input) {
-      enqueue_analysis(c, q);
-      RowParams rz{};
-      rz.spec_in = c.at<float2>(L.z);
-      rz.lin = dense_layout(p);
-      rz.real_out = c.at<float>(L.zs);
-      run_row(c, ROW_C2R, ST_F32, false, rz, q);
-    }
-    PixParams pp{};
-    pp.z = c.at<float>(L.zs);
-    pp.w = W;
-    pp.bw = BW;
-    pp.s = d_s;
-    pp.u = c.at<float>(L.us);
-    pp.partials = c.at<double>(L.parts) + L.nrow_parts * 4;
-    pp.n2 = n2;
-    pp.gamma = prm->gamma;
-    pp.q = q;
-    {
-      Timed tm(c.s, KC_PIXEL);
-      const dim3 g{unsigned(npix_blocks)}, b{256};
-      if (have_adjoint_input) {
-        if (stats) hipLaunchKernelGGL((k_pixel<true, true>), g, b, 0, c.s, pp);
-        else hipLaunchKernelGGL((k_pixel<false, true>), g, b, 0, c.s, pp);
-      } else {
-        if (stats) hipLaunchKernelGGL((k_pixel<true, false>), g, b, 0, c.s, pp);
-        else hipLaunchKernelGGL((k_pixel<false, false>), g, b, 0, c.s, pp);
-      }
-    }
-    // ---- v-update and b_v-update with S u, fused with the next adjoint's row FFT
-    enqueue_synthesis(c, c.at<float>(L.us), q);
-    RowParams rp{};
-    rp.spec_in = c.at<float2>(L.t1);
-    rp.lin = pl;
-    rp.spec_out = c.at<float2>(L.t2);
-    rp.lout = pl;
-    rp.g = c.ws + L.g;
-    rp.emit = last ? 0 : 1;
-    run_row(c, ROW_SOLVE, p->store, stats, rp, q * eta);
+    enqueue_iteration(c, d_s, prm->gamma, have_adjoint_input, stats, !last, d_hist ? d_hist + 4LL * it : nullptr);
     LAUNCHCHK("iteration");
     have_adjoint_input = true;
-    if (stats) {
-      enqueue_reduce(c, L.nrow_parts + npix_blocks, d_hist ? d_hist + 4LL * it : nullptr, prm->gamma);
-      LAUNCHCHK("reduce");
-    }
     done = it + 1;
     if (check || (last && h_stats)) {
-      HIPCHK(hipMemcpyAsync(last_tot, c.at<double>(L.sdev), 5 * 8, hipMemcpyDeviceToHost, c.s));
+      HIPCHK(hipMemcpyAsync(last_tot, c.at<double>(c.L.sdev), 5 * 8, hipMemcpyDeviceToHost, c.s));
       HIPCHK(hipStreamSynchronize(c.s));
       have_last = true;
       if (last_tot[4] != 0.0) return fail(SHS_E_NUMERIC, "non-finite residual at iteration " + std::to_string(it + 1));
       if (check && std::sqrt(last_tot[SLOT_DY2] + last_tot[SLOT_DB2]) <= prm->tol * rnorm) break;
     }
   }
-  if (d_u || d_labels) {
-    Timed tm(c.s, KC_OTHER);
-    hipLaunchKernelGGL(k_epilogue, dim3(unsigned(npix_blocks)), dim3(256), 0, c.s, W, q, n2, d_u, d_labels);
-    LAUNCHCHK("epilogue");
-  }
+  enqueue_epilogue(c, d_u, d_labels);
+  LAUNCHCHK("epilogue");
   if (h_stats) {
     shs_stats out{};
     out.iters_done = done;
@@ -906,11 +983,157 @@ shs_status shs_solve(const shs_plan* p, const shs_params* prm, const float* d_s,
       out.energy_surrogate = last_tot[SLOT_WS] + last_tot[SLOT_L1];
     }
     double e = 0.0;
-    st = energy_of(c, W, d_s, &e);
+    st = energy_of(c, c.at<float>(c.L.w), d_s, &e);
     if (st != SHS_OK) return st;
     out.energy = e;
     *h_stats = out;
   }
+  return SHS_OK;
+}
+
+shs_status shs_batch_create(int32_t count, const shs_shape* shapes, int device, shs_batch** out) {
+  if (!out || !shapes || count < 1) return fail(SHS_E_INVALID, "null argument or count < 1");
+  *out = nullptr;
+  shs_batch* b = new (std::nothrow) shs_batch{};
+  if (!b) return fail(SHS_E_NOMEM, "host allocation");
+  b->count = count;
+  b->device = device;
+  for (int i = 0; i < count; ++i) {
+    const shs_shape& s = shapes[i];
+    int found = -1;
+    for (size_t k = 0; k < b->plans.size(); ++k) {
+      const shs_plan* p = b->plans[k];
+      if (p->n == s.n && p->C == s.channels && p->q == s.q && p->J == s.J && p->store == s.store) found = int(k);
+    }
+    if (found < 0) {
+      shs_plan* p = nullptr;
+      const shs_status st = shs_plan_create(&s, device, &p);
+      if (st != SHS_OK) {
+        const std::string msg = g_err;
+        shs_batch_destroy(b);
+        return fail(st, "image " + std::to_string(i) + ": " + msg);
+      }
+      b->plans.push_back(p);
+      found = int(b->plans.size()) - 1;
+    }
+    b->plan_of.push_back(found);
+    b->ws_off.push_back(b->ws_total);
+    b->ws_total += align256(shs_workspace_bytes(b->plans[found]));
+  }
+  DeviceGuard dg(device);
+  const int nstreams = std::min(count, 8);
+  for (int k = 0; k < nstreams; ++k) {
+    hipStream_t s;
+    hipEvent_t e;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      shs_batch_destroy(b);
+      return fail(SHS_E_DEVICE, "batch stream creation");
+    }
+    b->streams.push_back(s);
+    b->join.push_back(e);
+  }
+  if (hipStreamCreateWithFlags(&b->main, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
+    shs_batch_destroy(b);
+    return fail(SHS_E_DEVICE, "batch stream creation");
+  }
+  *out = b;
+  return SHS_OK;
+}
+
+shs_status shs_batch_destroy(shs_batch* b) {
+  if (!b) return SHS_OK;
+  DeviceGuard dg(b->device);
+  b->drop_graphs();
+  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+  if (b->main) (void)hipStreamDestroy(b->main);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (shs_plan* p : b->plans) shs_plan_destroy(p);
+  delete b;
+  return SHS_OK;
+}
+
+size_t shs_batch_workspace_bytes(const shs_batch* b) { return b ? b->ws_total : 0; }
+
+shs_status shs_solve_batch(shs_batch* b, const shs_params* params, const float* const* d_s, void* d_ws,
+                           size_t ws_bytes, float* const* d_u, int32_t* const* d_labels, double* d_stats,
+                           void* stream) {
+  if (!b || !params || !d_s) return fail(SHS_E_INVALID, "null argument");
+  if (!d_ws || ws_bytes < b->ws_total) return fail(SHS_E_WORKSPACE, "batch workspace too small");
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) return fail(SHS_E_WORKSPACE, "workspace must be 256-byte aligned");
+  const int iters = params[0].iters;
+  for (int i = 0; i < b->count; ++i) {
+    const shs_status st = check_params(&params[i]);
+    if (st != SHS_OK) return fail(st, "image " + std::to_string(i) + ": " + g_err);
+    if (!d_s[i]) return fail(SHS_E_INVALID, "null data term of image " + std::to_string(i));
+    if (params[i].iters != iters) return fail(SHS_E_UNSUPPORTED, "all images of a batch run the same iteration count");
+    if (params[i].tol != 0.0 || params[i].resume) return fail(SHS_E_UNSUPPORTED, "batch solves take no tol / resume");
+  }
+  DeviceGuard dg(b->device);
+  // per-image contexts
+  std::vector<Ctx> ctx(b->count);
+  for (int i = 0; i < b->count; ++i) {
+    const shs_plan* p = b->plans[b->plan_of[i]];
+    shs_status st = make_ctx(p, static_cast<char*>(d_ws) + b->ws_off[i], shs_workspace_bytes(p), nullptr, ctx[i]);
+    if (st == SHS_OK) st = set_lambda(ctx[i], &params[i]);
+    if (st != SHS_OK) return fail(st, "image " + std::to_string(i) + ": " + g_err);
+    ctx[i].s = b->streams[i % b->streams.size()];
+  }
+  // graph cache key: every pointer and parameter baked into the graphs
+  std::vector<double> key;
+  key.push_back(double(reinterpret_cast<uintptr_t>(d_ws)));
+  key.push_back(double(reinterpret_cast<uintptr_t>(d_stats)));
+  key.push_back(iters);
+  for (int i = 0; i < b->count; ++i) {
+    key.push_back(double(reinterpret_cast<uintptr_t>(d_s[i])));
+    key.push_back(double(reinterpret_cast<uintptr_t>(d_u ? d_u[i] : nullptr)));
+    key.push_back(double(reinterpret_cast<uintptr_t>(d_labels ? d_labels[i] : nullptr)));
+    key.push_back(params[i].gamma);
+    for (int f = 0; f < ctx[i].p->eta; ++f) key.push_back(ctx[i].fw.lam[f]);
+  }
+  if (key != b->key) {
+    b->drop_graphs();
+    auto tail = [&](int i) {   // epilogue + statistics of image i
+      const Ctx& c = ctx[i];
+      enqueue_epilogue(c, d_u ? d_u[i] : nullptr, d_labels ? d_labels[i] : nullptr);
+      if (d_stats) hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(64), 0, c.s, c.at<double>(c.L.sdev), 5, d_stats + 5LL * i);
+    };
+    shs_status st = SHS_OK;
+    if (st == SHS_OK) st = b->capture([&] { for (int i = 0; i < b->count; ++i) enqueue_zero_state(ctx[i]); }, &b->g_init);
+    if (iters == 0) {
+      if (st == SHS_OK) st = b->capture([&] { for (int i = 0; i < b->count; ++i) tail(i); }, &b->g_last);
+    } else if (iters == 1) {
+      if (st == SHS_OK)
+        st = b->capture([&] {
+          for (int i = 0; i < b->count; ++i) { enqueue_iteration(ctx[i], d_s[i], params[i].gamma, false, true, false, nullptr); tail(i); }
+        }, &b->g_last);
+    } else {
+      if (st == SHS_OK)
+        st = b->capture([&] {
+          for (int i = 0; i < b->count; ++i) enqueue_iteration(ctx[i], d_s[i], params[i].gamma, false, false, true, nullptr);
+        }, &b->g_first);
+      if (st == SHS_OK)
+        st = b->capture([&] {
+          for (int i = 0; i < b->count; ++i) enqueue_iteration(ctx[i], d_s[i], params[i].gamma, true, false, true, nullptr);
+        }, &b->g_mid);
+      if (st == SHS_OK)
+        st = b->capture([&] {
+          for (int i = 0; i < b->count; ++i) { enqueue_iteration(ctx[i], d_s[i], params[i].gamma, true, true, false, nullptr); tail(i); }
+        }, &b->g_last);
+    }
+    if (st != SHS_OK) { b->drop_graphs(); return st; }
+    b->key = key;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Timed tm(s, KC_BATCH);
+  HIPCHK(hipGraphLaunch(b->g_init, s));
+  if (iters >= 2) {
+    HIPCHK(hipGraphLaunch(b->g_first, s));
+    for (int it = 1; it < iters - 1; ++it) HIPCHK(hipGraphLaunch(b->g_mid, s));
+  }
+  HIPCHK(hipGraphLaunch(b->g_last, s));
   return SHS_OK;
 }
 

@@ -24,7 +24,9 @@ def test_header_declares_expected_entry_points():
     syms = declared_symbols()
     for name in ["shs_plan_create", "shs_plan_destroy", "shs_workspace_bytes", "shs_state_bytes",
                  "shs_num_filters", "shs_filters", "shs_datacost", "shs_shearlet_forward",
-                 "shs_shearlet_adjoint", "shs_solve", "shs_energy", "shs_status_str", "shs_last_error"]:
+                 "shs_shearlet_adjoint", "shs_solve", "shs_energy", "shs_status_str", "shs_last_error",
+                 "shs_batch_create", "shs_batch_destroy", "shs_batch_workspace_bytes", "shs_solve_batch",
+                 "shs_profile_begin", "shs_profile_end"]:
         assert name in syms
 
 
@@ -59,6 +61,16 @@ def test_plan_validation(shape, code):
     st = L.shs_plan_create(ctypes.byref(pkg.ShsShape(*shape)), 0, ctypes.byref(h))
     assert st == code and not h.value
     assert len(L.shs_last_error()) > 0
+
+
+def test_batch_validation_without_device():
+    L = pkg.lib()
+    h = ctypes.c_void_p()
+    bad = (pkg.ShsShape * 2)(pkg.ShsShape(128, 1, 3, 2, 0), pkg.ShsShape(100, 1, 3, 2, 0))
+    assert L.shs_batch_create(0, bad, 0, ctypes.byref(h)) == pkg.SHS_E_INVALID
+    assert L.shs_batch_create(2, None, 0, ctypes.byref(h)) == pkg.SHS_E_INVALID
+    assert L.shs_batch_workspace_bytes(None) == 0 and L.shs_batch_destroy(None) == pkg.SHS_OK
+    assert L.shs_solve_batch(None, None, None, None, 0, None, None, None, None) == pkg.SHS_E_INVALID
 
 
 def test_null_arguments():

@@ -413,3 +413,77 @@ def test_unsupported_sizes_rejected():
         with pytest.raises(pkg.ShsError) as e:
             pkg.Plan(n, 1, 2, 2)
         assert e.value.status == pkg.SHS_E_UNSUPPORTED
+
+
+# ------------------------------------------------------------------ batches of images
+def _batch_inputs(workloads, stores):
+    pkg = _pkg()
+    s_list, plans = [], []
+    for w, st in zip(workloads, stores):
+        plan = pkg.Plan(w.n, w.channels, w.q, w.J, st)
+        s = torch.empty((w.q, w.n, w.n), dtype=torch.float32, device="cuda:0")
+        plan.datacost(dev_t(w.img), w.codebook, s)
+        s_list.append(s)
+        plans.append(plan)
+    return s_list, plans
+
+
+def test_batch_equals_eager_solves_and_replays():
+    from synth import make_c3_image
+    pkg = _pkg()
+    iters = 9
+    ws_ = [make_c3_image(i) for i in (1, 4, 5)] + [make_small(128, 3, 2, channels=3, seed=2),
+                                                   make_small(96, 5, 2, seed=3)]
+    stores = ["f32", "f32", "bf16", "f16", "f32"]
+    s_list, plans = _batch_inputs(ws_, stores)
+    batch = pkg.Batch([(w.n, w.channels, w.q, w.J, st) for w, st in zip(ws_, stores)])
+    bws = batch.new_workspace()
+    lams = [w.lam for w in ws_]
+    gammas = [w.gamma for w in ws_]
+    eager = []
+    for w, plan, s in zip(ws_, plans, s_list):
+        u = torch.empty_like(s)
+        lab = torch.empty((w.n, w.n), dtype=torch.int32, device="cuda:0")
+        st = plan.solve(s, plan.new_workspace(), w.lam, w.gamma, iters, u=u, labels=lab)
+        eager.append((u.cpu().numpy(), lab.cpu().numpy(), st))
+    u_list = [torch.full_like(s, -1.0) for s in s_list]
+    l_list = [torch.full((w.n, w.n), -1, dtype=torch.int32, device="cuda:0") for w in ws_]
+    stats = torch.zeros((len(ws_), 5), dtype=torch.float64, device="cuda:0")
+    for rep in range(3):
+        for u in u_list:
+            u.fill_(-1.0)
+        batch.solve(s_list, bws, lams, gammas, iters, u_list, l_list, stats)
+        torch.cuda.synchronize()
+        # eager work between replays
+        junk = torch.randn(1 << 20, device="cuda:0").sum().item()
+        for i, (eu, el, est) in enumerate(eager):
+            assert np.array_equal(u_list[i].cpu().numpy(), eu), (rep, i)
+            assert np.array_equal(l_list[i].cpu().numpy(), el), (rep, i)
+        st = stats.cpu().numpy()
+        for i, (_, _, est) in enumerate(eager):
+            assert st[i, 4] == 0.0
+            assert abs(np.sqrt(st[i, 1]) - est["r_primal"]) <= 1e-9 * max(1.0, est["r_primal"])
+            assert abs(st[i, 2] + st[i, 3] - est["energy_surrogate"]) <= 1e-9 * abs(est["energy_surrogate"])
+    del junk
+
+
+def test_batch_oracle_parity_and_zero_iterations():
+    from synth import make_c3_image
+    pkg = _pkg()
+    w = make_c3_image(1)      # 320 x 320, mixed-radix path
+    iters = 10
+    s_list, _ = _batch_inputs([w, make_small(64, 2, 1, seed=9)], ["f32", "f32"])
+    batch = pkg.Batch([(w.n, 1, w.q, w.J, "f32"), (64, 1, 2, 1, "f32")])
+    bws = batch.new_workspace()
+    u_list = [torch.empty_like(s) for s in s_list]
+    l_list = [torch.empty((s.shape[1], s.shape[2]), dtype=torch.int32, device="cuda:0") for s in s_list]
+    batch.solve(s_list, bws, [w.lam, [0.0, 0.1]], [w.gamma, 1.0], iters, u_list, l_list)
+    torch.cuda.synchronize()
+    r, s, B, lam_f = run_oracle(w, iters=iters, s=f32(s_list[0].cpu().numpy()))
+    assert np.max(np.abs(u_list[0].cpu().numpy() - r.w)) < 2e-5
+    assert np.mean(l_list[0].cpu().numpy() == r.labels) >= 0.999
+    batch.solve(s_list, bws, [w.lam, [0.0, 0.1]], [w.gamma, 1.0], 0, u_list, l_list)
+    torch.cuda.synchronize()
+    assert all(torch.count_nonzero(u).item() == 0 for u in u_list)
+    with pytest.raises(ValueError):
+        batch.solve(s_list[:1] + [s_list[0]], bws, [w.lam, w.lam], [1.0, 1.0], 3)
