@@ -19,6 +19,8 @@ import re
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -106,6 +108,73 @@ def run_gpu(args, w, store, iters, steps, warmup, profile):
                 eta=plan.eta, labels=labels, u=u)
 
 
+def run_batch(args):
+    """Batching form: 64 gray images of sizes 32*{3..24}, 2..6 labels, J=3, solved together
+    (shs_solve_batch: one captured graph per iteration for all images)."""
+    import torch
+    import paper_1112_1805_amd as pkg
+    from synth import make_c3
+    ws_ = make_c3(args.batch_count)
+    iters = args.iters if args.iters is not None else ws_[0].iters
+    store = args.store
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    batch = pkg.Batch([(w.n, 1, w.q, w.J, store) for w in ws_])
+    bws = batch.new_workspace()
+    plans = {}
+    s_list, u_list, l_list = [], [], []
+    for w in ws_:
+        key = (w.n, w.q)
+        if key not in plans:
+            plans[key] = pkg.Plan(w.n, 1, w.q, w.J, store)
+        s = torch.empty((w.q, w.n, w.n), dtype=torch.float32, device=dev)
+        plans[key].datacost(torch.tensor(w.img, dtype=torch.float32, device=dev), w.codebook, s)
+        s_list.append(s)
+        u_list.append(torch.empty_like(s))
+        l_list.append(torch.empty((w.n, w.n), dtype=torch.int32, device=dev))
+    stats = torch.empty((len(ws_), 5), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    lams = [w.lam for w in ws_]
+    gammas = [w.gamma for w in ws_]
+
+    def step():
+        batch.solve(s_list, bws, lams, gammas, iters, u_list, l_list, stats)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done (batch)")
+    pkg.shs_profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pkg.shs_profile_end()
+    st = stats.cpu().numpy()
+    assert np.all(st[:, 4] == 0.0), "non-finite residual in the batch"
+    its = args.steps * iters / dt
+    eta = 29
+    units = sum(w.n * w.n * w.q * eta for w in ws_)
+    ns = sorted({w.n for w in ws_})
+    out = {
+        "metric": "batch ADMM iters/s (all images advance one iteration) and Mpixel·label·filter/s",
+        "value": round(its, 3), "unit": "batch-iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"C3: {len(ws_)} gray images, sides {ns[0]}..{ns[-1]} (32*m), q 2..6, J=3 (29 filters), "
+                               f"{iters} ADMM iterations, {store} state, one captured graph per iteration",
+                   "images": len(ws_), "iters_per_step": iters, "state_storage": store,
+                   "coefficients_per_iter": units},
+        "mpixel_label_filter_per_s": round(its * units / 1e6, 1),
+        "ms_per_iter": round(dt / args.steps / iters * 1e3, 4),
+        "setup_ms": round(setup_ms, 1),
+        "workspace_gb": round(batch.workspace_bytes() / 1e9, 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def kernel_units(w, iters, eta, store_bytes):
     """Algorithmic bytes / flops per launch of each kernel class (one launch per iteration)."""
     n, q = w.n, w.q
@@ -130,7 +199,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3", "c4"])
     ap.add_argument("--store", default="f16", choices=["f32", "bf16", "f16"])
     ap.add_argument("--iters", type=int, default=None, help="ADMM iterations per step (default: workload's)")
     ap.add_argument("--cpu-iters", type=int, default=1, help="oracle iterations timed for the CPU baseline")
@@ -138,6 +207,7 @@ def main():
     ap.add_argument("--no-f32", action="store_true", help="skip the plain FP32 path run beside the main one")
     ap.add_argument("--no-hist", action="store_true",
                     help="residual reductions on the last iteration only (default: every iteration)")
+    ap.add_argument("--batch-count", type=int, default=64, help="images of the C3 batch")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy a 1 GiB buffer once (HBM counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -149,6 +219,9 @@ def main():
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "c3":
+        run_batch(args)
+        return
     w = workload(args.workload)
     iters = args.iters if args.iters is not None else w.iters
     store_bytes = 4 if args.store == "f32" else 2
