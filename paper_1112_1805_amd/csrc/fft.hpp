@@ -174,17 +174,27 @@ __device__ __forceinline__ void fft_sync() {
   }
 }
 
-// Row-style LDS addressing: FFT points contiguous with one pad slot per R points.
+// LDS addressing of one FFT's points.  `at<R>(q, rr)` is point q * R + rr (rr < R); the
+// FFT stages below only use that form, with q = a per-thread base plus a compile-time
+// constant, so every LDS access is one base register plus an immediate offset.
+// Row style: points contiguous with one pad slot per R points.
 template <int R>
 struct RowAddr {
   float2* base;
-  __device__ __forceinline__ float2* operator()(int pos) const { return base + pos + pos / R; }
+  __device__ __forceinline__ float2* operator()(unsigned pos) const { return base + (pos + pos / R); }
+  template <int RQ>
+  __device__ __forceinline__ float2* at(int q, int rr) const {
+    static_assert(RQ == R, "row addressing pads every R points");
+    return base + (q * (R + 1) + rr);
+  }
 };
-// Column-style LDS addressing: W FFTs interleaved, point pos of FFT c at pos*W + c.
+// Column style: W FFTs interleaved, point pos of FFT c at pos*W + c.
 template <int W>
 struct ColAddr {
   float2* base;  // already offset by the column c
-  __device__ __forceinline__ float2* operator()(int pos) const { return base + pos * W; }
+  __device__ __forceinline__ float2* operator()(unsigned pos) const { return base + pos * W; }
+  template <int RQ>
+  __device__ __forceinline__ float2* at(int q, int rr) const { return base + (q * RQ + rr) * W; }
 };
 
 // In-register/LDS Stockham FFT of length L.  On entry a[r] holds point t + r*T; on exit
@@ -195,44 +205,46 @@ template <int L, int R, int RM, bool INV, int SK, class Addr>
 __device__ __forceinline__ void fft_run(cpx (&a)[R], const Addr& lds, int t,
                                         const float2* __restrict__ tw, int twstep) {
   static_assert(R * R * RM == L && R % RM == 0, "FFT configuration");
-  constexpr int T = L / R;
-  // stage 0: radix R, Ns = 1
+  constexpr int T = L / R;                 // = R * RM
+  const int tq = int(unsigned(t) / R);     // t = tq * R + tr
+  const int tr = int(unsigned(t) % R);
+  // stage 0: radix R, Ns = 1; point r of this thread goes to position t * R + r
   RegDFT<R, INV>::run(a);
   fft_sync<SK>();
-  static_for<R>([&](auto r) { st(lds(t * R + r), a[r]); });
+  static_for<R>([&](auto r) { st(lds.template at<R>(t, r), a[r]); });
   fft_sync<SK>();
   if constexpr (RM > 1) {
-    // middle stage: radix RM, Ns = R; this thread runs R/RM butterflies bf = t + u*T
+    // middle stage: radix RM, Ns = R; this thread runs R/RM butterflies bf = t + u*T with
+    // inputs bf + r*L/RM = (tq + u*RM + r*R) * R + tr and twiddle index k = bf mod R = tr
     constexpr int U = R / RM;
     cpx b[R];
     static_for<U>([&](auto u) {
-      const int bf = t + u * T;
-      static_for<RM>([&](auto r) { b[u * RM + r] = ld(lds(bf + r * (L / RM))); });
+      static_for<RM>([&](auto r) { b[u * RM + r] = ld(lds.template at<R>(tq + u * RM + r * R, tr)); });
     });
     fft_sync<SK>();
+    cpx w[RM];
+    static_for<RM>([&](auto r) {
+      if constexpr (r > 0) w[r] = ld(tw + (r * tr) * (L / (R * RM)) * twstep);
+    });
     static_for<U>([&](auto u) {
-      const int bf = t + u * T;
-      const int k = bf % R;
       cpx c[RM];
       static_for<RM>([&](auto r) {
         cpx v = b[u * RM + r];
-        if constexpr (r > 0) {
-          cpx w = ld(tw + (r * k) * (L / (R * RM)) * twstep);
-          v = INV ? cmulc(v, w) : cmul(v, w);
-        }
+        if constexpr (r > 0) v = INV ? cmulc(v, w[r]) : cmul(v, w[r]);
         c[r] = v;
       });
       RegDFT<RM, INV>::run(c);
-      const int obase = (bf / R) * (R * RM) + k;
-      static_for<RM>([&](auto r) { st(lds(obase + r * R), c[r]); });
+      // outputs (bf / R) * R * RM + k + r * R = ((tq + u*RM) * RM + r) * R + tr
+      static_for<RM>([&](auto r) { st(lds.template at<R>((tq + u * RM) * RM + r, tr), c[r]); });
     });
     fft_sync<SK>();
   }
-  // last stage: radix R, Ns = L/R, butterfly bf = t, k = t
+  // last stage: radix R, Ns = L/R, butterfly bf = t; input t + r*T = (tq + r*RM) * R + tr
+  const int twt = t * twstep;
   static_for<R>([&](auto r) {
-    cpx v = ld(lds(t + r * T));
+    cpx v = ld(lds.template at<R>(tq + r * RM, tr));
     if constexpr (r > 0) {
-      cpx w = ld(tw + (r * t) * twstep);
+      cpx w = ld(tw + r * twt);
       v = INV ? cmulc(v, w) : cmul(v, w);
     }
     a[r] = v;

@@ -227,12 +227,40 @@ template <int N> struct ColCfg : ColGeom<N> {
 // Half-spectrum planes are stored in strips: strip s of a plane (columns [s W, s W + W))
 // is one contiguous block of N * W bins, bin (k0, k1) at k0 * W + (k1 mod W).  A column
 // pass streams a whole block; a row pass (8 consecutive rows per block) reads 8 * W
-// contiguous bins per strip.
+// contiguous bins per strip.  tix gives the bin offset of column ip of a plane, with
+// floor division for negative ip: a plane of `pitch` columns (pitch a multiple of W)
+// spans offsets [0, pitch * N), and every ip outside [0, pitch) lands outside that span
+// (negative offsets wrap to above 2^31 as unsigned byte offsets).
 template <int N>
-__device__ __forceinline__ long long tix(int ip, int row) {
+__device__ __forceinline__ int tix(int ip, int row) {
   constexpr int W = ColGeom<N>::W;
-  return (long long)(ip / W) * (N * W) + row * W + (ip & (W - 1));
+  constexpr int S = W == 4 ? 2 : W == 8 ? 3 : 4;
+  static_assert((1 << S) == W, "strip width");
+  return (ip >> S) * (N * W) + row * W + (ip & (W - 1));
 }
+
+// Raw buffer view of one spectrum plane.  The hardware range check of buffer accesses
+// (offset >= size) makes loads outside the plane return zero and drops such stores, so
+// the wedge window of a row needs no branches.
+struct PlaneBuf {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ PlaneBuf(const float2* base, int bins)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(base), short(0), bins * 8, 0x00020000)) {}
+  __device__ __forceinline__ cpx load(int bin) const {
+    // (elements are taken by value: a bit cast of a vector-element lvalue would read
+    // element 0 for both)
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, unsigned(bin) * 8u, 0, 0);
+    const unsigned lo = v[0], hi = v[1];
+    return cpx{__uint_as_float(lo), __uint_as_float(hi)};
+  }
+  __device__ __forceinline__ void store(int bin, cpx x) const {
+    using u2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0, 0));
+    u2 v;
+    v[0] = __float_as_uint(x.x);
+    v[1] = __float_as_uint(x.y);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, unsigned(bin) * 8u, 0, 0);
+  }
+};
 
 // ---------------------------------------------------------------- row pass
 enum RowMode { ROW_SOLVE = 0, ROW_C2R = 1, ROW_R2C = 2, ROW_PRIME = 3, ROW_ENERGY = 4 };
@@ -276,8 +304,12 @@ struct SpecLayout {
 };
 __device__ __forceinline__ void plane_geom(const SpecLayout& L, int f, int& cb, int& pitch, long long& off) {
   if (L.tab) {
+    // f is uniform over the block: keep the entry in scalar registers
     const int4 e = L.tab[f];
-    cb = e.x; pitch = e.y; off = (long long)(unsigned)e.z | ((long long)e.w << 32);
+    cb = __builtin_amdgcn_readfirstlane(e.x);
+    pitch = __builtin_amdgcn_readfirstlane(e.y);
+    off = (long long)(unsigned)__builtin_amdgcn_readfirstlane(e.z) |
+          ((long long)__builtin_amdgcn_readfirstlane(e.w) << 32);
   } else {
     cb = 0; pitch = L.P; off = 0;
   }
@@ -298,19 +330,42 @@ struct RowParams {
   FilterWeights fw;        // passed by value (kernel argument memory)
 };
 
+// Column offset of the row bins at k = t + r*T, k - cb and M - k - cb, as strip-tiled
+// bin offsets: when T is a whole number of strips they step by a constant.
+template <int N, int SIGN>
+__device__ __forceinline__ int row_bin(int base_ip, int base_off, int r, int row) {
+  using G = RowGeom<N>;
+  constexpr int W = ColGeom<N>::W;
+  if constexpr (G::T % W == 0) {
+    return base_off + SIGN * r * (G::T * N);
+  } else {
+    return tix<N>(base_ip + SIGN * r * G::T, row);
+  }
+}
+
 // Inverse real FFT of a half-spectrum row (unnormalised): X[0..M] -> x[0..N) with
-// point pair (2p, 2p+1) of p = t + r*T in a[r] = (x[2p], x[2p+1]).  The row holds the
+// point pair (2p, 2p+1) of p = t + r*T in a[r] = (x[2p], x[2p+1]).  The plane holds the
 // columns [cb, cb + pitch); other bins are zero.
 template <int N, class Addr>
 __device__ __forceinline__ void row_c2r(cpx (&a)[RowGeom<N>::R], const float2* __restrict__ X, int row, int cb,
                                         int pitch, const Addr& A, int t, const float2* __restrict__ tw) {
   using G = RowGeom<N>;
+  const PlaneBuf B(X, pitch * N);
+  const int ip0 = t - cb, im0 = G::M - t - cb;
+  const int op0 = tix<N>(ip0, row), om0 = tix<N>(im0, row);
+  // Chunk r covers k in [r T, r T + T) for every row of the wave; whether it meets the
+  // window (directly or mirrored) is uniform, so chunks outside it are skipped whole.
+  cpx xp[G::R], xm[G::R];
+  static_for<G::R>([&](auto r) {
+    constexpr int k0 = r * G::T;
+    xp[r] = cpx{0.f, 0.f};
+    xm[r] = cpx{0.f, 0.f};
+    if (k0 < cb + pitch && k0 + G::T > cb) xp[r] = B.load(row_bin<N, 1>(ip0, op0, r, row));
+    if (k0 <= G::M - cb && k0 + G::T > G::M - cb - pitch) xm[r] = B.load(row_bin<N, -1>(im0, om0, r, row));
+  });
   static_for<G::R>([&](auto r) {
     const int k = t + r * G::T;
-    const unsigned ip = unsigned(k - cb), im = unsigned(G::M - k - cb);
-    const cpx xp = ip < unsigned(pitch) ? ld(X + tix<N>(int(ip), row)) : cpx{0.f, 0.f};
-    const cpx xm = im < unsigned(pitch) ? conj(ld(X + tix<N>(int(im), row))) : cpx{0.f, 0.f};
-    const cpx s = xp + xm, d = xp - xm;
+    const cpx s = xp[r] + conj(xm[r]), d = xp[r] - conj(xm[r]);
     const cpx w = conj(ld(tw + k));          // W_N^{-k}
     a[r] = s + mul_i(cmul(d, w));
   });
@@ -324,21 +379,24 @@ __device__ __forceinline__ void row_r2c(cpx (&a)[RowGeom<N>::R], float2* __restr
                                         const Addr& A, int t, const float2* __restrict__ tw) {
   using G = RowGeom<N>;
   fft_run<G::M, G::R, G::RM, false, SYNC_WAVE>(a, A, t, tw, 2);
+  const int tq = int(unsigned(t) / G::R), tr = int(unsigned(t) % G::R);
   fft_sync<SYNC_WAVE>();
-  static_for<G::R>([&](auto r) { st(A(t + r * G::T), a[r]); });
+  static_for<G::R>([&](auto r) { st(A.template at<G::R>(tq + r * G::RM, tr), a[r]); });
   fft_sync<SYNC_WAVE>();
+  const PlaneBuf B(X, pitch * N);
+  const int ip0 = t - cb, op0 = tix<N>(ip0, row);
   static_for<G::R>([&](auto r) {
-    const int k = t + r * G::T;
-    const unsigned ip = unsigned(k - cb);
-    if (ip < unsigned(pitch)) {
+    constexpr int k0 = r * G::T;
+    if (k0 < cb + pitch && k0 + G::T > cb) {
+      const int k = t + k0;
       const cpx yk = a[r];
-      const cpx ym = conj(ld(A((G::M - k) & (G::M - 1))));
+      const cpx ym = conj(ld(A(unsigned(G::M - k) & unsigned(G::M - 1))));
       const cpx s = yk + ym, d = yk - ym;
       const cpx w = ld(tw + k);                 // W_N^{k}
-      st(X + tix<N>(int(ip), row), (s - mul_i(cmul(d, w))) * 0.5f);
+      B.store(row_bin<N, 1>(ip0, op0, r, row), (s - mul_i(cmul(d, w))) * 0.5f);
     }
   });
-  if (t == 0 && unsigned(G::M - cb) < unsigned(pitch)) st(X + tix<N>(G::M - cb, row), cpx{a[0].x - a[0].y, 0.f});
+  if (t == 0) B.store(tix<N>(G::M - cb, row), cpx{a[0].x - a[0].y, 0.f});
 }
 
 template <int N, int MODE, int ST, bool STATS>
