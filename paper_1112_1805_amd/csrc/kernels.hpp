@@ -212,16 +212,20 @@ __global__ void k_datacost(const float* __restrict__ img, int C, Codebook cb, in
 // adjacent columns per block, W * T threads.  Strip s holds columns [s W, s W + W) (only
 // those <= N/2 exist).  Strips are stored as contiguous blocks, so W only trades block
 // size against occupancy (W = 4 at N = 1024: 256 threads, 32 KB LDS, 3 blocks per CU).
+// WPE is the occupancy hint of the filtered column passes (waves per SIMD).  At N = 2048
+// they run at two waves and load the next filter's spectrum column during the current
+// FFT (PREFETCH); at three waves that extra register set would spill.
 template <int N> struct ColGeom;
-template <> struct ColGeom<64>   { static constexpr int R = 8,  RM = 1, W = 16; };
-template <> struct ColGeom<128>  { static constexpr int R = 8,  RM = 2, W = 16; };
-template <> struct ColGeom<256>  { static constexpr int R = 16, RM = 1, W = 16; };
-template <> struct ColGeom<512>  { static constexpr int R = 16, RM = 2, W = 8; };
-template <> struct ColGeom<1024> { static constexpr int R = 16, RM = 4, W = 4; };
-template <> struct ColGeom<2048> { static constexpr int R = 16, RM = 8, W = 4; };
+template <> struct ColGeom<64>   { static constexpr int R = 8,  RM = 1, W = 16, WPE = 3; };
+template <> struct ColGeom<128>  { static constexpr int R = 8,  RM = 2, W = 16, WPE = 3; };
+template <> struct ColGeom<256>  { static constexpr int R = 16, RM = 1, W = 16, WPE = 3; };
+template <> struct ColGeom<512>  { static constexpr int R = 16, RM = 2, W = 8,  WPE = 3; };
+template <> struct ColGeom<1024> { static constexpr int R = 16, RM = 4, W = 4,  WPE = 3; };
+template <> struct ColGeom<2048> { static constexpr int R = 16, RM = 8, W = 4,  WPE = 2; };
 template <int N> struct ColCfg : ColGeom<N> {
   static constexpr int T = N / ColGeom<N>::R;
   static constexpr int THREADS = ColGeom<N>::W * T;
+  static constexpr bool PREFETCH = ColGeom<N>::WPE <= 2;
 };
 
 // Half-spectrum planes are stored in strips: strip s of a plane (columns [s W, s W + W))
@@ -238,6 +242,10 @@ __device__ __forceinline__ int tix(int ip, int row) {
   static_assert((1 << S) == W, "strip width");
   return (ip >> S) * (N * W) + row * W + (ip & (W - 1));
 }
+
+// A bin index whose byte offset (times 8, modulo 2^32) stays far above any plane size,
+// also after adding a row or column stride: loads from it read zero.
+constexpr int kOutOfPlane = -(1 << 26);
 
 // Raw buffer view of one spectrum plane.  The hardware range check of buffer accesses
 // (offset >= size) makes loads outside the plane return zero and drops such stores, so
@@ -520,7 +528,47 @@ struct ColParams {
   float2* part;           // partial accumulators [slot][labels][N][W]
   const float2* tw;       // exp(-2 pi i m / N)
   int P, eta, labels;
+  int nnz;                // stored filter values in psiw (< 2^29)
   float inv_n2;           // 1 / N^2 (normalisation of the inverse 2-D DFT)
+};
+
+constexpr int kItemMax = 16;   // filters per column work item
+
+// A work item's per-filter data, staged in LDS once per block: the column window of
+// every (filter, column) pair and the plane geometry {cb, pitch, off_lo, off_hi} of
+// every filter.  Without it each filter step waits on three dependent loads.
+template <int W> struct ItemStage {
+  int4 win[kItemMax][W];
+  int4 geo[kItemMax];
+};
+template <int N>
+__device__ __forceinline__ void stage_item(const ColParams& p, int4 it, ItemStage<ColCfg<N>::W>& st) {
+  constexpr int W = ColCfg<N>::W, M = N / 2;
+  for (int e = threadIdx.x; e < it.z * W; e += ColCfg<N>::THREADS) {
+    const int i = e / W, cc = e % W;
+    const int j = p.flist[it.y + i];
+    const int k1 = it.x * W + cc;
+    st.win[i][cc] = k1 <= M ? p.pwin[j * (M + 1) + k1] : make_int4(0, 0, 0, 0);
+    if (cc == 0) st.geo[i] = p.tl.tab[j];
+  }
+}
+__device__ __forceinline__ long long geo_off(int4 g) { return (long long)(unsigned)g.z | ((long long)g.w << 32); }
+
+// Filter values of one column window, psi_j(k0, k1) for k0 = t + r T (zero outside the
+// window; a wave with no lane inside the window for some r skips that load).
+struct PsiBuf {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ explicit PsiBuf(const ColParams& p)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p.psiw), short(0), p.nnz * 4, 0x00020000)) {}
+  template <int N, int R, int T>
+  __device__ __forceinline__ void load(int4 win, int t, float (&v)[R]) const {
+    const unsigned base = unsigned(t - win.x);
+    static_for<R>([&](auto rr) {
+      const unsigned rel = (base + unsigned(rr * T)) & unsigned(N - 1);
+      v[rr] = 0.f;
+      if (rel < unsigned(win.y)) v[rr] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (unsigned(win.z) + rel) * 4u, 0, 0));
+    });
+  }
 };
 
 // psi_j(k0, k1) from the compact window of column k1 (zero outside the window).
@@ -551,31 +599,35 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per
 }
 
 // Synthesis: for every filter j of the item, T1[l, j] = colIFFT(psi_j * U_l / N^2) on the
-// item's strip (only columns inside filter j's range exist in T1).
+// item's strip (only columns inside filter j's range exist in T1).  The next filter's
+// values are loaded while the current inverse FFT runs.
 template <int N>
-__global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_col_syn(ColParams p) {
+__global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(ColGeom<N>::WPE))) void k_col_syn(ColParams p) {
   using G = ColCfg<N>;
   constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
   __shared__ float2 lds[N * W];
+  __shared__ ItemStage<W> stg;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int4 it = p.items[blockIdx.x];
   const int k1 = it.x * W + c;
   const bool valid = k1 <= M;
   const int l = blockIdx.y;
   const ColAddr<W> A{lds + c};
+  stage_item<N>(p, it, stg);
   cpx uh[R];
   const float2* U = p.in + l * (long long)N * p.P + (long long)it.x * (N * W) + c;
   static_for<R>([&](auto r) { uh[r] = valid ? ld(U + (t + r * T) * W) : cpx{0.f, 0.f}; });
+  __syncthreads();
+  const PsiBuf PB(p);
+  float ps[R];
+  PB.load<N, R, T>(stg.win[0][c], t, ps);
   for (int i = 0; i < it.z; ++i) {
-    const int j = p.flist[it.y + i];
-    const int4 win = valid ? p.pwin[j * (M + 1) + k1] : make_int4(0, 0, 0, 0);
     cpx a[R];
-    static_for<R>([&](auto r) { a[r] = uh[r] * (psi_at<N>(p, win, t + r * T) * p.inv_n2); });
+    static_for<R>([&](auto r) { a[r] = uh[r] * (ps[r] * p.inv_n2); });
+    if (i + 1 < it.z) PB.load<N, R, T>(stg.win[i + 1][c], t, ps);
     fft_run<N, R, G::RM, true, SYNC_BLOCK>(a, A, t, p.tw, 1);
-    int cb, pitch;
-    long long off;
-    plane_geom(p.tl, j, cb, pitch, off);
-    float2* o = p.out + l * p.tl.ls + off + (long long)(it.x - cb / W) * (N * W) + c;
+    const int4 geo = stg.geo[i];
+    float2* o = p.out + l * p.tl.ls + geo_off(geo) + (long long)(it.x - geo.x / W) * (N * W) + c;
     if (valid) {
       static_for<R>([&](auto r) { st(o + (t + r * T) * W, a[r]); });
     }
@@ -597,31 +649,45 @@ __device__ __forceinline__ void col_finish(const ColParams& p, cpx (&acc)[ColCfg
 
 // Analysis: ACC = sum_j psi_j * colFFT(T2[l, j]) over the item's filters.  A strip with a
 // single item finishes here (Z_l = colIFFT(ACC / N^2)); otherwise the item's partial
-// accumulator is stored and k_col_final sums the strip's items in order.
+// accumulator is stored and k_col_final sums the strip's items in order.  With PREFETCH
+// the next filter's spectrum column is loaded while the current FFT runs.
 template <int N>
-__global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_col_ana(ColParams p) {
+__global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(ColGeom<N>::WPE))) void k_col_ana(ColParams p) {
   using G = ColCfg<N>;
   constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
   __shared__ float2 lds[N * W];
+  __shared__ ItemStage<W> stg;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int4 it = p.items[blockIdx.x];
   const int k1 = it.x * W + c;
   const bool valid = k1 <= M;
   const int l = blockIdx.y;
   const ColAddr<W> A{lds + c};
-  cpx acc[R];
+  stage_item<N>(p, it, stg);
+  __syncthreads();
+  // T2 column of item filter i; columns past N/2 are never written and read as zero
+  auto load_col = [&](int i, cpx (&v)[R]) {
+    const int4 geo = stg.geo[i];
+    const PlaneBuf B(p.in + l * p.tl.ls + geo_off(geo), geo.y * N);
+    const int base = valid ? (it.x - geo.x / W) * (N * W) + t * W + c : kOutOfPlane;
+    static_for<R>([&](auto r) { v[r] = B.load(base + r * (T * W)); });
+  };
+  cpx acc[R], nx[R];
   static_for<R>([&](auto r) { acc[r] = cpx{0.f, 0.f}; });
+  if constexpr (G::PREFETCH) load_col(0, nx);
+  const PsiBuf PB(p);
   for (int i = 0; i < it.z; ++i) {
-    const int j = p.flist[it.y + i];
-    int cb, pitch;
-    long long off;
-    plane_geom(p.tl, j, cb, pitch, off);
-    const float2* in = p.in + l * p.tl.ls + off + (long long)(it.x - cb / W) * (N * W) + c;
     cpx a[R];
-    static_for<R>([&](auto r) { a[r] = valid ? ld(in + (t + r * T) * W) : cpx{0.f, 0.f}; });
+    if constexpr (G::PREFETCH) {
+      static_for<R>([&](auto r) { a[r] = nx[r]; });
+      if (i + 1 < it.z) load_col(i + 1, nx);
+    } else {
+      load_col(i, a);
+    }
+    float ps[R];
+    PB.load<N, R, T>(stg.win[i][c], t, ps);
     fft_run<N, R, G::RM, false, SYNC_BLOCK>(a, A, t, p.tw, 1);
-    const int4 win = valid ? p.pwin[j * (M + 1) + k1] : make_int4(0, 0, 0, 0);
-    static_for<R>([&](auto r) { acc[r] = acc[r] + a[r] * psi_at<N>(p, win, t + r * T); });
+    static_for<R>([&](auto r) { acc[r] = acc[r] + a[r] * ps[r]; });
   }
   if (it.w < 0) {
     col_finish<N>(p, acc, t, k1, valid, l, A);

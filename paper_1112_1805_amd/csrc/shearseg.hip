@@ -369,6 +369,7 @@ ColParams col_params(const Ctx& c, int labels) {
   cp.P = p->P;
   cp.eta = p->eta;
   cp.labels = labels;
+  cp.nnz = int(p->nnz);
   cp.inv_n2 = 1.0f / (float(p->n) * float(p->n));
   return cp;
 }
@@ -535,7 +536,7 @@ shs_status build_pruned_layout(shs_plan* p) {
     tcol[j] = make_int4(cb, pitch, int(toff & 0xffffffffLL), int(toff >> 32));
     toff += (long long)n * pitch;
   }
-  if (off > 0x7fffffffLL) return fail(SHS_E_UNSUPPORTED, "filter bank too large");
+  if (off >= (1LL << 29)) return fail(SHS_E_UNSUPPORTED, "filter bank too large");
   p->nnz = off;
   p->t_ls = toff;
   // 3. work lists
@@ -548,8 +549,8 @@ shs_status build_pruned_layout(shs_plan* p) {
     flist.insert(flist.end(), per_strip[s].begin(), per_strip[s].end());
   }
   const long long pairs = (long long)flist.size();
-  const int fc_syn = int(std::min<long long>(16, std::max<long long>(1, (pairs * p->q + 1249) / 2500)));
-  const int fc_ana = int(std::min<long long>(16, std::max<long long>(2, (pairs * p->q + 749) / 1500)));
+  const int fc_syn = int(std::min<long long>(kItemMax, std::max<long long>(1, (pairs * p->q + 1249) / 2500)));
+  const int fc_ana = int(std::min<long long>(kItemMax, std::max<long long>(2, (pairs * p->q + 749) / 1500)));
   std::vector<int4> isyn, iana;
   std::vector<int2> strips;
   build_items(per_strip, strip_off, fc_syn, false, isyn, nullptr, nullptr);
