@@ -114,7 +114,7 @@ def run_batch(args):
     import torch
     import paper_1112_1805_amd as pkg
     from synth import make_c3
-    ws_ = make_c3(args.batch_count)
+    ws_ = make_c3(args.batch_count or 64)
     iters = args.iters if args.iters is not None else ws_[0].iters
     store = args.store
     dev = torch.device("cuda:0")
@@ -175,6 +175,97 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_denoise(args):
+    """Standalone transform form: shrinkage denoising S^T S_lambda S of a batch of 1024^2
+    gray images with the J=4 system (61 filters), shs_shearlet_denoise."""
+    import torch
+    import paper_1112_1805_amd as pkg
+    from synth import make_denoise
+    n, J, group = 1024, 4, 8
+    count = args.batch_count if args.batch_count else 16
+    sigma = 0.1
+    clean, noisy = make_denoise(count, n, sigma)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    plan = pkg.Plan(n, 1, group, J)
+    ws = plan.new_workspace()
+    # per-filter thresholds 3 sigma ||psi_j||: white noise of variance sigma^2 has variance
+    # sigma^2 sum_w psi_j(w)^2 / N^2 in the coefficients of filter j (half spectrum, mirrored)
+    bank = torch.empty((plan.eta, n, n // 2 + 1), dtype=torch.float32, device=dev)
+    plan.filters(bank)
+    sq = (bank.double() ** 2).sum(dim=1)
+    energy = (sq[:, 0] + sq[:, n // 2] + 2 * sq[:, 1:n // 2].sum(dim=1)).cpu().numpy()
+    lam = np.float32(3.0 * sigma * np.sqrt(energy) / n)
+    lam[0] = 0.0
+    f = torch.tensor(noisy, dtype=torch.float32, device=dev)
+    out = torch.empty_like(f)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    for i in range(args.warmup):
+        plan.shearlet_denoise(f, lam, ws, out=out)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done (denoise)")
+    pkg.shs_profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.shearlet_denoise(f, lam, ws, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = pkg.shs_profile_end()
+    ips = args.steps * count / dt
+    eta = plan.eta
+    # quality on the synthetic truth (sanity, not a benchmark figure)
+    ct = torch.tensor(clean, dtype=torch.float32, device=dev)
+    def psnr(x):
+        mse = torch.mean((x.double() - ct.double()) ** 2).item()
+        return round(10 * np.log10(1.0 / mse), 2)
+    # dominant kernel: the shrink row pass, two real FFTs of length N per coefficient row
+    lg = n.bit_length() - 1
+    kname, (launches, total_ms) = max(prof.items(), key=lambda kv: kv[1][1])
+    per_launch_rows = {"row_shrink": group * eta * n}
+    roofline = None
+    if kname in per_launch_rows:
+        flops = per_launch_rows[kname] * 2 * 2.5 * n * lg
+        avg_s = total_ms / launches / 1e3
+        ach = flops / avg_s / 1e12
+        roofline = {"bound": "alu", "achieved": round(ach, 2), "peak": FP32_VALU_PEAK_TFS, "unit": "TFLOP/s",
+                    "frac": round(ach / FP32_VALU_PEAK_TFS, 4), "traffic": None, "kernel": kname,
+                    "algorithmic_per_launch": flops, "avg_launch_ms": round(avg_s * 1e3, 5)}
+    out_json = {
+        "metric": "shrinkage denoising S^T S_lambda S, images/s at 1024^2, J=4 (61 filters)",
+        "value": round(ips, 3), "unit": "images/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"denoise: {count} gray 1024x1024 cartoon-texture images + N(0, {sigma}^2) noise, "
+                               f"J=4 (61 filters), thresholds 3 sigma ||psi_j|| (low-pass kept), groups of {group}",
+                   "images": count, "filters": eta},
+        "mpixel_filter_per_s": round(ips * n * n * eta / 1e6, 1),
+        "roofline": roofline,
+        "kernel_breakdown_ms": {k: {"launches": v[0], "total_ms": round(v[1], 4), "avg_ms": round(v[1] / v[0], 5)}
+                                for k, v in prof.items()},
+        "psnr_db": {"noisy": psnr(f), "denoised": psnr(out)},
+        "setup_ms": round(setup_ms, 1),
+        "source_hash": source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        workers = min(16, os.cpu_count() or 1)
+        os.environ["ORACLE_FFT_WORKERS"] = str(workers)
+        import oracle
+        oracle.transform.WORKERS = workers
+        B = oracle.filter_bank(n, J)
+        lam_f = np.float64(lam)
+        x = np.float32(noisy[0]).astype(np.float64)
+        t0 = time.perf_counter()
+        ref = oracle.denoise(x, B, lam_f)
+        cdt = time.perf_counter() - t0
+        err = float(np.linalg.norm(out[0].double().cpu().numpy() - ref) / np.linalg.norm(x))
+        out_json["cpu_baseline"] = {"value": round(1.0 / cdt, 4), "unit": "images/s", "cores": workers,
+                                    "kind": "oracle",
+                                    "sample": f"1 image of the same batch, FP64 oracle ({workers} scipy.fft workers); "
+                                              f"{cdt:.1f} s; GPU vs oracle norm-relative difference {err:.2e}"}
+    print(json.dumps(out_json), flush=True)
+
+
 def kernel_units(w, iters, eta, store_bytes):
     """Algorithmic bytes / flops per launch of each kernel class (one launch per iteration)."""
     n, q = w.n, w.q
@@ -199,7 +290,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3", "c4", "denoise"])
     ap.add_argument("--store", default="f16", choices=["f32", "bf16", "f16"])
     ap.add_argument("--iters", type=int, default=None, help="ADMM iterations per step (default: workload's)")
     ap.add_argument("--cpu-iters", type=int, default=1, help="oracle iterations timed for the CPU baseline")
@@ -207,7 +298,8 @@ def main():
     ap.add_argument("--no-f32", action="store_true", help="skip the plain FP32 path run beside the main one")
     ap.add_argument("--no-hist", action="store_true",
                     help="residual reductions on the last iteration only (default: every iteration)")
-    ap.add_argument("--batch-count", type=int, default=64, help="images of the C3 batch")
+    ap.add_argument("--batch-count", type=int, default=None,
+                    help="images of the batch modes (default 64 for c3, 16 for denoise)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy a 1 GiB buffer once (HBM counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -221,6 +313,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "c3":
         run_batch(args)
+        return
+    if args.workload == "denoise":
+        run_denoise(args)
         return
     w = workload(args.workload)
     iters = args.iters if args.iters is not None else w.iters

@@ -125,17 +125,28 @@ shs_status shs_filters(const shs_plan* plan, float* d_psi, void* stream);
 shs_status shs_datacost(const shs_plan* plan, const float* d_img, const float* h_codebook, float p,
                         float* d_s, void* stream);
 
-/* Discrete shearlet transform S (Section 2, eq. (wichtig)) of `count` images (1..q):
- * d_f float32 [count][N][N]  ->  d_c float32 [count][eta][N][N],
- * c_j = ifft2(psi_j * fft2(f)).  Uses the workspace. */
+/* Discrete shearlet transform S (Section 2, eq. (wichtig)) of `count` images (any
+ * count >= 1; processed in groups of at most q): d_f float32 [count][N][N]  ->
+ * d_c float32 [count][eta][N][N], c_j = ifft2(psi_j * fft2(f)).  Uses the workspace. */
 shs_status shs_shearlet_forward(const shs_plan* plan, int32_t count, const float* d_f, float* d_c,
                                 void* d_ws, size_t ws_bytes, void* stream);
 
 /* Adjoint (= inverse, by the Parseval property) transform S^T (Section 2, inverse
  * paragraph): d_c float32 [count][eta][N][N]  ->  d_f float32 [count][N][N],
- * f = ifft2(sum_j psi_j * fft2(c_j)). */
+ * f = ifft2(sum_j psi_j * fft2(c_j)); any count >= 1. */
 shs_status shs_shearlet_adjoint(const shs_plan* plan, int32_t count, const float* d_c, float* d_f,
                                 void* d_ws, size_t ws_bytes, void* stream);
+
+/* Shrinkage denoising S^T S_lambda S of `count` images (any count >= 1): the transform of
+ * Section 2, the componentwise soft shrinkage of Section 3 (S_lambda(x) = x - clip(x,
+ * +-lambda), zero for |x| <= lambda) with threshold lambda_j on every coefficient of
+ * filter j, and the adjoint; with all lambda = 0 it returns f (Theorem 2.2).
+ * h_lambda: HOST float32, lambda_len = J+1 (per scale, low-pass first, as shs_params) or
+ * eta (per filter), entries finite and >= 0.  d_f, d_out: float32 [count][N][N] (may be
+ * the same buffer).  The coefficient images are never stored: the shrinkage runs inside
+ * the row pass between the forward and the adjoint column passes.  Uses the workspace. */
+shs_status shs_shearlet_denoise(const shs_plan* plan, int32_t count, const float* h_lambda, int32_t lambda_len,
+                                const float* d_f, float* d_out, void* d_ws, size_t ws_bytes, void* stream);
 
 /* ADMM for (problemSegmentationADMM) (Section 3): starting from v = w = b = 0 (or the
  * workspace state if params->resume), run params->iters iterations of

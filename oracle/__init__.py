@@ -31,14 +31,14 @@ is parity unpinned (the images are not published).
 """
 from .meyer import meyer_v, meyer_b, psi1_hat, psi2_hat, phi_1d
 from .filters import freq_index, filter_list, num_filters, filter_bank, filter_scale_index
-from .transform import fft2, ifft2, naive_dft2, forward, adjoint
+from .transform import fft2, ifft2, naive_dft2, forward, adjoint, denoise
 from .prox import soft_shrink, project_simplex, project_simplex_paper, project_simplex_bruteforce
 from .model import datacost, lambda_per_filter, admm, energy, labels_of, AdmmResult
 
 __all__ = [
     "meyer_v", "meyer_b", "psi1_hat", "psi2_hat", "phi_1d",
     "freq_index", "filter_list", "num_filters", "filter_bank", "filter_scale_index",
-    "fft2", "ifft2", "naive_dft2", "forward", "adjoint",
+    "fft2", "ifft2", "naive_dft2", "forward", "adjoint", "denoise",
     "soft_shrink", "project_simplex", "project_simplex_paper", "project_simplex_bruteforce",
     "datacost", "lambda_per_filter", "admm", "energy", "labels_of", "AdmmResult",
 ]

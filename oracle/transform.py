@@ -62,3 +62,12 @@ def adjoint(c: np.ndarray, bank: np.ndarray) -> np.ndarray:
     for j in range(bank.shape[0]):
         acc += bank[j] * fft2(c[j])
     return ifft2(acc).real
+
+
+def denoise(f: np.ndarray, bank: np.ndarray, lam_f) -> np.ndarray:
+    """S^T S_lambda S f: the coefficients of eq. (wichtig), Section 3's soft shrinkage
+    S_lambda applied to every coefficient of filter j with threshold lam_f[j], then the
+    adjoint of the inverse-transform paragraph.  f [N][N] real, lam_f [eta] >= 0."""
+    from .prox import soft_shrink
+    c = forward(f, bank)
+    return adjoint(soft_shrink(c, np.asarray(lam_f, dtype=np.float64)[:, None, None]), bank)

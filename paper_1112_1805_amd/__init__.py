@@ -64,6 +64,7 @@ _SIGS = {
     "shs_datacost": (_I32, [_VP, _VP, ctypes.POINTER(ctypes.c_float), ctypes.c_float, _VP, _VP]),
     "shs_shearlet_forward": (_I32, [_VP, _I32, _VP, _VP, _VP, _SZ, _VP]),
     "shs_shearlet_adjoint": (_I32, [_VP, _I32, _VP, _VP, _VP, _SZ, _VP]),
+    "shs_shearlet_denoise": (_I32, [_VP, _I32, ctypes.POINTER(ctypes.c_float), _I32, _VP, _VP, _VP, _SZ, _VP]),
     "shs_solve": (_I32, [_VP, ctypes.POINTER(ShsParams), _VP, _VP, _SZ, _VP, _VP, _VP,
                          ctypes.POINTER(ShsStats), _VP]),
     "shs_energy": (_I32, [_VP, ctypes.POINTER(ShsParams), _VP, _VP, _VP, _SZ,
@@ -214,6 +215,20 @@ class Plan:
         _check(lib().shs_shearlet_adjoint(self.handle, count, _ptr(c), _ptr(f), _ptr(ws), ws.numel(),
                                           _stream(stream)), "shs_shearlet_adjoint")
         return f
+
+    def shearlet_denoise(self, f, lam, ws, out=None, stream=None):
+        """S^T S_lambda S f (shs_shearlet_denoise); `lam` per scale (J+1) or per filter (eta)."""
+        count = f.shape[0]
+        _expect(f, (count, self.n, self.n), "f32", "d_f")
+        if out is None:
+            import torch
+            out = torch.empty_like(f)
+        _expect(out, (count, self.n, self.n), "f32", "d_out")
+        arr = np.ascontiguousarray(np.asarray(lam, dtype=np.float32).ravel())
+        _check(lib().shs_shearlet_denoise(self.handle, count, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                          arr.size, _ptr(f), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)),
+               "shs_shearlet_denoise")
+        return out
 
     def solve(self, s, ws, lam, gamma, iters, u=None, labels=None, hist=None, want_stats=True,
               tol=0.0, check_every=1, resume=False, stream=None):

@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void k_row_g(RowParams p, GenParams gp) {
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   float2* res = b0;
 
-  if constexpr (MODE == ROW_SOLVE || MODE == ROW_C2R || MODE == ROW_ENERGY) {
+  if constexpr (MODE == ROW_SOLVE || MODE == ROW_C2R || MODE == ROW_ENERGY || MODE == ROW_SHRINK) {
     int cb, pitch;
     long long off;
     plane_geom(p.lin, ch % p.lin.nf, cb, pitch, off);
@@ -209,7 +209,14 @@ __global__ __launch_bounds__(256) void k_row_g(RowParams p, GenParams gp) {
       res[k] = make_float2(n0 - 2.f * nb0, n1 - 2.f * nb1);
     }
   }
-  if constexpr (MODE == ROW_R2C || MODE == ROW_PRIME || MODE == ROW_SOLVE) {
+  if constexpr (MODE == ROW_SHRINK) {
+    const float th = p.fw.thr[j];
+    for (int k = lane; k < M; k += 64) {
+      const float2 c = res[k];
+      res[k] = make_float2(c.x - fminf(fmaxf(c.x, -th), th), c.y - fminf(fmaxf(c.y, -th), th));
+    }
+  }
+  if constexpr (MODE == ROW_R2C || MODE == ROW_PRIME || MODE == ROW_SOLVE || MODE == ROW_SHRINK) {
     bool emit = true;
     if constexpr (MODE == ROW_SOLVE) emit = p.emit != 0;
     if (emit) {

@@ -271,7 +271,7 @@ struct PlaneBuf {
 };
 
 // ---------------------------------------------------------------- row pass
-enum RowMode { ROW_SOLVE = 0, ROW_C2R = 1, ROW_R2C = 2, ROW_PRIME = 3, ROW_ENERGY = 4 };
+enum RowMode { ROW_SOLVE = 0, ROW_C2R = 1, ROW_R2C = 2, ROW_PRIME = 3, ROW_ENERGY = 4, ROW_SHRINK = 5 };
 
 // Row FFTs have complex length M = N/2: (R, RM) with R * R * RM = M.
 template <int M> struct RowFft;
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(256) void k_row(RowParams p) {
     static_for<G::R>([&](auto r) { gv[r] = S::load_pair(gp + 2 * (t + r * G::T)); });
   }
 
-  if constexpr (MODE == ROW_SOLVE || MODE == ROW_C2R || MODE == ROW_ENERGY) {
+  if constexpr (MODE == ROW_SOLVE || MODE == ROW_C2R || MODE == ROW_ENERGY || MODE == ROW_SHRINK) {
     int cb, pitch;
     long long off;
     const int f = ch % p.lin.nf;
@@ -488,7 +488,14 @@ __global__ __launch_bounds__(256) void k_row(RowParams p) {
     // term live, doubling the register footprint.
     if constexpr (STATS && MODE == ROW_SOLVE) __asm__ volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[3]));
   }
-  if constexpr (MODE == ROW_R2C || MODE == ROW_PRIME || MODE == ROW_SOLVE) {
+  if constexpr (MODE == ROW_SHRINK) {
+    // soft shrinkage of the coefficient row (Section 3's S_lambda, threshold thr_j)
+    const float th = p.fw.thr[j];
+    static_for<G::R>([&](auto r) {
+      a[r] = cpx{a[r].x - fminf(fmaxf(a[r].x, -th), th), a[r].y - fminf(fmaxf(a[r].y, -th), th)};
+    });
+  }
+  if constexpr (MODE == ROW_R2C || MODE == ROW_PRIME || MODE == ROW_SOLVE || MODE == ROW_SHRINK) {
     bool emit = true;
     if constexpr (MODE == ROW_SOLVE) emit = p.emit != 0;
     if (emit) {

@@ -79,11 +79,11 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // ---------------------------------------------------------------- kernel timing
 enum KClass {
   KC_ROW_SOLVE, KC_COL_SYN, KC_COL_ANA, KC_COL_FINAL, KC_COL_FWD, KC_ROW_C2R, KC_ROW_R2C, KC_ROW_PRIME,
-  KC_ROW_ENERGY, KC_PIXEL, KC_REDUCE, KC_OTHER, KC_BATCH, KC_COUNT
+  KC_ROW_ENERGY, KC_PIXEL, KC_REDUCE, KC_OTHER, KC_BATCH, KC_ROW_SHRINK, KC_COUNT
 };
 const char* const kKClassName[KC_COUNT] = {"row_solve", "col_syn", "col_ana", "col_final", "col_fwd", "row_c2r",
                                            "row_r2c", "row_prime", "row_energy", "pixel", "reduce", "other",
-                                           "batch_solve"};
+                                           "batch_solve", "row_shrink"};
 
 struct Prof {
   std::mutex mu;
@@ -205,6 +205,7 @@ struct Pipe {
       case ROW_C2R: row_t<ROW_C2R, ST_F32, false>(rp, channels, s); break;
       case ROW_R2C: row_t<ROW_R2C, ST_F32, false>(rp, channels, s); break;
       case ROW_ENERGY: row_t<ROW_ENERGY, ST_F32, true>(rp, channels, s); break;
+      case ROW_SHRINK: row_t<ROW_SHRINK, ST_F32, false>(rp, channels, s); break;
     }
   }
   static void col(const shs_plan*, int kind, const ColParams& cp, int nblocks, int labels, hipStream_t s) {
@@ -244,6 +245,7 @@ struct GenPipe {
       case ROW_C2R: row_t<ROW_C2R, ST_F32, false>(p, rp, channels, s); break;
       case ROW_R2C: row_t<ROW_R2C, ST_F32, false>(p, rp, channels, s); break;
       case ROW_ENERGY: row_t<ROW_ENERGY, ST_F32, true>(p, rp, channels, s); break;
+      case ROW_SHRINK: row_t<ROW_SHRINK, ST_F32, false>(p, rp, channels, s); break;
     }
   }
   static void col(const shs_plan* p, int kind, const ColParams& cp, int nblocks, int labels, hipStream_t s) {
@@ -312,6 +314,7 @@ int row_class(int mode) {
     case ROW_R2C: return KC_ROW_R2C;
     case ROW_PRIME: return KC_ROW_PRIME;
     case ROW_ENERGY: return KC_ROW_ENERGY;
+    case ROW_SHRINK: return KC_ROW_SHRINK;
   }
   return KC_OTHER;
 }
@@ -871,44 +874,91 @@ shs_status shs_datacost(const shs_plan* p, const float* d_img, const float* h_co
   return SHS_OK;
 }
 
+// The transform entry points take any number of images and run them in groups of at
+// most q (the plan's label count sizes the workspace's spectra).
 shs_status shs_shearlet_forward(const shs_plan* p, int32_t count, const float* d_f, float* d_c, void* d_ws,
                                 size_t ws_bytes, void* stream) {
   if (!p || !d_f || !d_c) return fail(SHS_E_INVALID, "null argument");
-  if (count < 1 || count > p->q) return fail(SHS_E_INVALID, "count must be in 1..q");
+  if (count < 1) return fail(SHS_E_INVALID, "count must be >= 1");
   DeviceGuard dg(p->device);
   Ctx c;
   shs_status st = make_ctx(p, d_ws, ws_bytes, stream, c);
   if (st != SHS_OK) return st;
-  enqueue_synthesis(c, d_f, count);
-  RowParams rp{};
-  rp.spec_in = c.at<float2>(c.L.t1);
-  rp.lin = pruned_layout(p);
-  rp.real_out = d_c;
-  run_row(c, ROW_C2R, ST_F32, false, rp, count * p->eta);
-  LAUNCHCHK("forward");
+  const long long n2 = (long long)p->n * p->n;
+  for (int i0 = 0; i0 < count; i0 += p->q) {
+    const int k = std::min(p->q, count - i0);
+    enqueue_synthesis(c, d_f + i0 * n2, k);
+    RowParams rp{};
+    rp.spec_in = c.at<float2>(c.L.t1);
+    rp.lin = pruned_layout(p);
+    rp.real_out = d_c + (long long)i0 * p->eta * n2;
+    run_row(c, ROW_C2R, ST_F32, false, rp, k * p->eta);
+    LAUNCHCHK("forward");
+  }
   return SHS_OK;
 }
 
 shs_status shs_shearlet_adjoint(const shs_plan* p, int32_t count, const float* d_c, float* d_f, void* d_ws,
                                 size_t ws_bytes, void* stream) {
   if (!p || !d_f || !d_c) return fail(SHS_E_INVALID, "null argument");
-  if (count < 1 || count > p->q) return fail(SHS_E_INVALID, "count must be in 1..q");
+  if (count < 1) return fail(SHS_E_INVALID, "count must be >= 1");
   DeviceGuard dg(p->device);
   Ctx c;
   shs_status st = make_ctx(p, d_ws, ws_bytes, stream, c);
   if (st != SHS_OK) return st;
-  RowParams rp{};
-  rp.real_in = d_c;
-  rp.spec_out = c.at<float2>(c.L.t2);
-  rp.lout = pruned_layout(p);
-  run_row(c, ROW_R2C, ST_F32, false, rp, count * p->eta);
-  enqueue_analysis(c, count);
-  RowParams rz{};
-  rz.spec_in = c.at<float2>(c.L.z);
-  rz.lin = dense_layout(p);
-  rz.real_out = d_f;
-  run_row(c, ROW_C2R, ST_F32, false, rz, count);
-  LAUNCHCHK("adjoint");
+  const long long n2 = (long long)p->n * p->n;
+  for (int i0 = 0; i0 < count; i0 += p->q) {
+    const int k = std::min(p->q, count - i0);
+    RowParams rp{};
+    rp.real_in = d_c + (long long)i0 * p->eta * n2;
+    rp.spec_out = c.at<float2>(c.L.t2);
+    rp.lout = pruned_layout(p);
+    run_row(c, ROW_R2C, ST_F32, false, rp, k * p->eta);
+    enqueue_analysis(c, k);
+    RowParams rz{};
+    rz.spec_in = c.at<float2>(c.L.z);
+    rz.lin = dense_layout(p);
+    rz.real_out = d_f + i0 * n2;
+    run_row(c, ROW_C2R, ST_F32, false, rz, k);
+    LAUNCHCHK("adjoint");
+  }
+  return SHS_OK;
+}
+
+// S^T S_lambda S: forward transform, soft shrinkage of every coefficient and the adjoint,
+// with the shrinkage inside the row pass between the two column passes (the coefficient
+// images are never stored).
+shs_status shs_shearlet_denoise(const shs_plan* p, int32_t count, const float* h_lambda, int32_t lambda_len,
+                                const float* d_f, float* d_out, void* d_ws, size_t ws_bytes, void* stream) {
+  if (!p || !d_f || !d_out || !h_lambda) return fail(SHS_E_INVALID, "null argument");
+  if (count < 1) return fail(SHS_E_INVALID, "count must be >= 1");
+  DeviceGuard dg(p->device);
+  Ctx c;
+  shs_status st = make_ctx(p, d_ws, ws_bytes, stream, c);
+  if (st != SHS_OK) return st;
+  shs_params prm{};
+  prm.lambda = h_lambda;
+  prm.lambda_len = lambda_len;
+  prm.gamma = 1.f;
+  if ((st = set_lambda(c, &prm)) != SHS_OK) return st;
+  const long long n2 = (long long)p->n * p->n;
+  for (int i0 = 0; i0 < count; i0 += p->q) {
+    const int k = std::min(p->q, count - i0);
+    enqueue_synthesis(c, d_f + i0 * n2, k);
+    RowParams rp{};
+    rp.spec_in = c.at<float2>(c.L.t1);
+    rp.lin = pruned_layout(p);
+    rp.spec_out = c.at<float2>(c.L.t2);
+    rp.lout = pruned_layout(p);
+    run_row(c, ROW_SHRINK, ST_F32, false, rp, k * p->eta);
+    enqueue_analysis(c, k);
+    RowParams rz{};
+    rz.spec_in = c.at<float2>(c.L.z);
+    rz.lin = dense_layout(p);
+    rz.real_out = d_out + i0 * n2;
+    run_row(c, ROW_C2R, ST_F32, false, rz, k);
+    LAUNCHCHK("denoise");
+  }
   return SHS_OK;
 }
 

@@ -222,6 +222,22 @@ def make_c4(index: int = 0, n: int = 2048) -> Workload:
     return Workload("C4", img[None], levels[:, None].copy(), J=4, lam=lam, gamma=1.0, iters=300, truth=lab)
 
 
+def make_denoise(count: int = 16, n: int = 1024, sigma: float = 0.1):
+    """Denoising inputs: `count` gray cartoon-texture images (curved Voronoi with 24 sites,
+    8 grey levels, half of the regions textured as in C1/C4) and their noisy versions with
+    N(0, sigma^2) noise.  Returns (clean, noisy), each [count][n][n] float64."""
+    clean = np.empty((count, n, n))
+    noisy = np.empty((count, n, n))
+    for i in range(count):
+        rng = _rng(5, i)
+        levels = np.linspace(0.0, 1.0, 8)
+        lab = curved_voronoi_labels(n, 8, 24, rng)
+        textured = rng.uniform(size=8) < 0.5
+        clean[i] = levels[lab] + oriented_texture(n, lab, 8, 0.1, rng, textured)
+        noisy[i] = clean[i] + rng.normal(0.0, sigma, size=(n, n))
+    return clean, noisy
+
+
 def make_small(n: int, q: int, J: int, channels: int = 1, seed: int = 0, lam: float = 0.1,
                gamma: float = 1.0, iters: int = 20, noise: float = 0.1) -> Workload:
     """Small ellipse workload of any size, for parity tests (seeded by `seed`)."""

@@ -134,12 +134,75 @@ def test_transform_edge_cases():
     plan.shearlet_forward(torch.zeros((1, n, n), device="cuda:0"), c, ws)
     torch.cuda.synchronize()
     assert torch.count_nonzero(c).item() == 0
-    with pytest.raises(pkg.ShsError):
-        plan.shearlet_forward(torch.zeros((3, n, n), device="cuda:0"),
-                              torch.empty((3, plan.eta, n, n), device="cuda:0"), ws)   # count > q
+    # count > q runs in groups of q: each image's coefficients equal its own transform
+    f3 = dev_t(random_image(n, seed=21, channels=3))
+    c3 = torch.empty((3, plan.eta, n, n), device="cuda:0")
+    plan.shearlet_forward(f3, c3, ws)
+    r3 = torch.empty_like(f3)
+    plan.shearlet_adjoint(c3, r3, ws)
+    torch.cuda.synchronize()
+    for i in range(3):
+        plan.shearlet_forward(f3[i:i + 1].contiguous(), c, ws)
+        torch.cuda.synchronize()
+        assert torch.equal(c[0], c3[i])
+    assert torch.max(torch.abs(r3 - f3)).item() < 1e-5
     with pytest.raises(pkg.ShsError) as e:
         plan.shearlet_forward(torch.zeros((1, n, n), device="cuda:0"), c, ws[:1024])
     assert e.value.status == pkg.SHS_E_WORKSPACE
+
+
+# ------------------------------------------------------------------ denoising S^T S_lambda S
+DENOISE_CASES = [(64, 2, 2, 5), (128, 3, 3, 3), (96, 2, 2, 3), (160, 3, 4, 2), (256, 4, 1, 1), (512, 3, 2, 2)]
+
+
+@pytest.mark.parametrize("n,J,q,count", DENOISE_CASES)
+def test_denoise_matches_oracle(n, J, q, count):
+    # count > q exercises the grouping; 96 and 160 the mixed-radix path
+    pkg = _pkg()
+    plan = pkg.Plan(n, 1, q, J)
+    ws = plan.new_workspace()
+    f = random_image(n, seed=7 * n + J, channels=count).astype(np.float32)
+    rng = np.random.default_rng(n + count)
+    lam_scale = np.float32([0.0] + list(rng.uniform(0.02, 0.3, size=J)))
+    lam_filter = np.float32(rng.uniform(0.0, 0.3, size=plan.eta))
+    B = O.filter_bank(n, J)
+    for lam, lam_f in ((lam_scale, O.lambda_per_filter(f32(lam_scale), J)), (lam_filter, f32(lam_filter))):
+        out = plan.shearlet_denoise(dev_t(f), lam, ws)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        for i in range(count):
+            ref = O.denoise(f32(f[i]), B, lam_f)
+            assert np.linalg.norm(got[i] - ref) < 1e-5 * np.linalg.norm(f[i])
+
+
+def test_denoise_full_size_and_edge_cases():
+    pkg = _pkg()
+    n, J = 1024, 4
+    plan = pkg.Plan(n, 1, 2, J)
+    ws = plan.new_workspace()
+    f = random_image(n, seed=9, channels=2).astype(np.float32)
+    fd = dev_t(f)
+    # lambda = 0: the identity (Theorem 2.2)
+    out0 = plan.shearlet_denoise(fd, np.zeros(J + 1, np.float32), ws)
+    lam = np.float32([0.0, 0.05, 0.1, 0.2, 0.4])
+    out = plan.shearlet_denoise(fd, lam, ws)
+    # in place (d_out == d_f) gives the same bits
+    fin = fd.clone()
+    plan.shearlet_denoise(fin, lam, ws, out=fin)
+    torch.cuda.synchronize()
+    assert torch.linalg.vector_norm((out0 - fd).double()).item() < 1e-5 * torch.linalg.vector_norm(fd.double()).item()
+    assert torch.equal(fin, out)
+    ref = O.denoise(f32(f[1]), O.filter_bank(n, J), O.lambda_per_filter(f32(lam), J))
+    assert np.linalg.norm(out[1].cpu().numpy() - ref) < 1e-5 * np.linalg.norm(f[1])
+    # huge thresholds: zero output
+    big = plan.shearlet_denoise(fd, np.full(J + 1, 1e30, np.float32), ws)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(big).item() == 0
+    for bad in (np.float32([0.0, 0.1]), np.float32([0.0, -0.1, 0.1, 0.1, 0.1]),
+                np.float32([0.0, np.nan, 0.1, 0.1, 0.1])):
+        with pytest.raises(pkg.ShsError) as e:
+            plan.shearlet_denoise(fd, bad, ws)
+        assert e.value.status == pkg.SHS_E_INVALID
 
 
 # ------------------------------------------------------------------ data term
