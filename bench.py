@@ -116,7 +116,7 @@ def run_batch(args):
     from synth import make_c3
     ws_ = make_c3(args.batch_count or 64)
     iters = args.iters if args.iters is not None else ws_[0].iters
-    store = args.store
+    store = args.store if args.store_set else "f32"     # the batching form is specified in FP32
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     batch = pkg.Batch([(w.n, 1, w.q, w.J, store) for w in ws_])
@@ -291,7 +291,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3", "c4", "denoise"])
-    ap.add_argument("--store", default="f16", choices=["f32", "bf16", "f16"])
+    ap.add_argument("--store", default=None, choices=["f32", "bf16", "f16"],
+                    help="state storage (default f16 for c0-c2/c4, f32 for the c3 batch)")
     ap.add_argument("--iters", type=int, default=None, help="ADMM iterations per step (default: workload's)")
     ap.add_argument("--cpu-iters", type=int, default=1, help="oracle iterations timed for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -303,6 +304,9 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy a 1 GiB buffer once (HBM counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
+    args.store_set = args.store is not None
+    if args.store is None:
+        args.store = "f16"
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on exactly one GPU (the path has no multi-GPU mode); "

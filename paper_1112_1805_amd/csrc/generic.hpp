@@ -17,6 +17,10 @@ struct FftPlan {
   int L;                     // transform length
   int ns;                    // number of stages
   int radix[kMaxStages];     // product = L
+  // Division by the stage stride Ns_s = radix[0] * ... * radix[s-1] without a divide:
+  // x / Ns_s = (umulhi(x, mag[s]) + x) >> sh[s] for x < 2^21 (constants from the host).
+  unsigned mag[kMaxStages];
+  int sh[kMaxStages];
 };
 
 // ---------------------------------------------------------------- small DFTs
@@ -63,17 +67,21 @@ __device__ __forceinline__ void dft_any(cpx (&a)[R]) {
 // ---------------------------------------------------------------- one Stockham stage
 // `items` = W interleaved transforms x (L / R) butterflies, spread over nthr threads.
 // Element `pos` of transform c lives at buf[pos * W + c].  tw: exp(-2 pi i m / (L*twstep)).
-template <int R, bool INV>
-__device__ __forceinline__ void gstage(const float2* __restrict__ src, float2* __restrict__ dst, int L, int Ns, int W,
-                                       int nthr, int tid, const float2* __restrict__ tw, int twstep) {
+template <int R, bool INV, int W>
+__device__ __forceinline__ void gstage(const float2* __restrict__ src, float2* __restrict__ dst, int L, int Ns,
+                                       unsigned mag, int sh, int nthr, int tid, const float2* __restrict__ tw,
+                                       int twstep) {
+  static_assert((W & (W - 1)) == 0, "strip width is a power of two");
   const int nb = L / R;
   const int items = nb * W;
   const int tws = (L / (Ns * R)) * twstep;
   for (int it = tid; it < items; it += nthr) {
-    const int c = it % W, bf = it / W;
-    const int k = bf % Ns;
+    const int c = it & (W - 1);
+    const unsigned bf = unsigned(it) / W;
+    const unsigned g = (__umulhi(bf, mag) + bf) >> sh;     // bf / Ns
+    const int k = int(bf - g * unsigned(Ns));
     cpx a[R];
-    static_for<R>([&](auto i) { a[i] = ld(src + (bf + i * nb) * W + c); });
+    static_for<R>([&](auto i) { a[i] = ld(src + (int(bf) + i * nb) * W + c); });
     if (Ns > 1) {
       static_for<R - 1>([&](auto i1) {
         constexpr int i = i1 + 1;
@@ -82,34 +90,36 @@ __device__ __forceinline__ void gstage(const float2* __restrict__ src, float2* _
       });
     }
     dft_any<R, INV>(a);
-    const int ob = (bf / Ns) * Ns * R + k;
+    const int ob = int(g) * Ns * R + k;
     static_for<R>([&](auto i) { st(dst + (ob + i * Ns) * W + c, a[i]); });
   }
 }
 
 // Full transform: data in b0 (natural order) -> result (natural order) in the returned buffer.
-template <bool INV, int SK>
-__device__ float2* gfft(float2* b0, float2* b1, const FftPlan& pl, int W, int nthr, int tid,
+template <bool INV, int SK, int W>
+__device__ float2* gfft(float2* b0, float2* b1, const FftPlan& pl, int nthr, int tid,
                         const float2* __restrict__ tw, int twstep) {
   float2* src = b0;
   float2* dst = b1;
   int Ns = 1;
   for (int s = 0; s < pl.ns; ++s) {
     const int r = pl.radix[s];
+    const unsigned mg = pl.mag[s];
+    const int sh = pl.sh[s];
     switch (r) {
-      case 2: gstage<2, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
-      case 3: gstage<3, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
-      case 4: gstage<4, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
-      case 5: gstage<5, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
-      case 7: gstage<7, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
-      case 8: gstage<8, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
-      case 9: gstage<9, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
-      case 11: gstage<11, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
-      case 13: gstage<13, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
-      case 16: gstage<16, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
-      case 17: gstage<17, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
-      case 19: gstage<19, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
-      case 23: gstage<23, INV>(src, dst, pl.L, Ns, W, nthr, tid, tw, twstep); break;
+      case 2: gstage<2, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
+      case 3: gstage<3, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
+      case 4: gstage<4, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
+      case 5: gstage<5, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
+      case 7: gstage<7, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
+      case 8: gstage<8, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
+      case 9: gstage<9, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
+      case 11: gstage<11, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
+      case 13: gstage<13, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
+      case 16: gstage<16, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
+      case 17: gstage<17, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
+      case 19: gstage<19, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
+      case 23: gstage<23, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
       default: break;
     }
     fft_sync<SK>();
@@ -123,11 +133,7 @@ __device__ float2* gfft(float2* b0, float2* b1, const FftPlan& pl, int W, int nt
 
 // ---------------------------------------------------------------- generic geometry
 constexpr int kGW = 4;          // strip width of the generic path
-constexpr int kGRows = 4;       // rows per block (one row per wave)
 
-__device__ __forceinline__ long long tix_rt(int ip, int row, int n) {
-  return (long long)(ip / kGW) * (n * kGW) + row * kGW + (ip % kGW);
-}
 
 struct GenParams {
   FftPlan prow;   // length N/2
@@ -136,20 +142,27 @@ struct GenParams {
 };
 
 // ---------------------------------------------------------------- generic row pass
-// Same modes and data contract as k_row; one row per wave, the row's two half-length
-// complex transforms live in LDS (2 x N/2 bins per wave, dynamic shared memory).
-template <int MODE, int ST, bool STATS>
+// Same modes and data contract as k_row.  Each wave transforms RW rows at once, stored
+// interleaved in LDS (bin k of row c at k * RW + c, two half-length complex buffers per
+// wave, dynamic shared memory), so that a stage's butterflies of all RW rows share the
+// wave's lanes; memory phases walk one row at a time (coalesced along the row).
+__device__ __forceinline__ int tix_g(int ip, int row, int n) {
+  return (ip >> 2) * (n * kGW) + row * kGW + (ip & (kGW - 1));     // floor for negative ip
+}
+
+template <int MODE, int ST, bool STATS, int RW>
 __global__ __launch_bounds__(256) void k_row_g(RowParams p, GenParams gp) {
+  static_assert(kGW == 4, "tix_g assumes strips of 4 columns");
   using S = Store<ST>;
   extern __shared__ float2 gsm[];
   __shared__ double red[4 * 4];
   const int n = gp.n, M = n / 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int row = blockIdx.x * kGRows + wave;
+  const int row0 = (blockIdx.x * 4 + wave) * RW;
   const int ch = blockIdx.y;
   const int j = ch % p.eta;
-  float2* b0 = gsm + wave * 2 * M;
-  float2* b1 = b0 + M;
+  float2* b0 = gsm + wave * 2 * M * RW;
+  float2* b1 = b0 + M * RW;
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   float2* res = b0;
 
@@ -157,63 +170,69 @@ __global__ __launch_bounds__(256) void k_row_g(RowParams p, GenParams gp) {
     int cb, pitch;
     long long off;
     plane_geom(p.lin, ch % p.lin.nf, cb, pitch, off);
-    const float2* X = p.spec_in + (ch / p.lin.nf) * p.lin.ls + off;
-    for (int k = lane; k < M; k += 64) {
-      const unsigned ip = unsigned(k - cb), im = unsigned(M - k - cb);
-      const cpx xp = ip < unsigned(pitch) ? ld(X + tix_rt(int(ip), row, n)) : cpx{0.f, 0.f};
-      const cpx xm = im < unsigned(pitch) ? conj(ld(X + tix_rt(int(im), row, n))) : cpx{0.f, 0.f};
-      const cpx s = xp + xm, d = xp - xm;
-      const cpx w = conj(ld(p.tw + k));
-      st(b0 + k, s + mul_i(cmul(d, w)));
+    const PlaneBuf B(p.spec_in + (ch / p.lin.nf) * p.lin.ls + off, pitch * n);
+    for (int c = 0; c < RW; ++c) {
+      const int row = row0 + c;
+      for (int k = lane; k < M; k += 64) {
+        // bins outside the plane's columns are out-of-range buffer loads: zero
+        const cpx xp = B.load(tix_g(k - cb, row, n));
+        const cpx xm = conj(B.load(tix_g(M - k - cb, row, n)));
+        const cpx s = xp + xm, d = xp - xm;
+        const cpx w = conj(ld(p.tw + k));
+        st(b0 + k * RW + c, s + mul_i(cmul(d, w)));
+      }
     }
     fft_sync<SYNC_WAVE>();
-    res = gfft<true, SYNC_WAVE>(b0, b1, gp.prow, 1, 64, lane, p.tw, 2);
+    res = gfft<true, SYNC_WAVE, RW>(b0, b1, gp.prow, 64, lane, p.tw, 2);
   }
   if constexpr (MODE == ROW_C2R) {
-    float* out = p.real_out + ch * p.real_cs + (long long)row * n;
-    for (int k = lane; k < M; k += 64) {
-      const float2 v = res[k];
-      *reinterpret_cast<float2*>(out + 2 * k) = v;
+    for (int c = 0; c < RW; ++c) {
+      float* out = p.real_out + ch * p.real_cs + (long long)(row0 + c) * n;
+      for (int k = lane; k < M; k += 64) *reinterpret_cast<float2*>(out + 2 * k) = res[k * RW + c];
     }
     return;
   }
   if constexpr (MODE == ROW_ENERGY) {
-    for (int k = lane; k < M; k += 64) acc[SLOT_L1] += fabsf(res[k].x) + fabsf(res[k].y);
+    for (int e = lane; e < M * RW; e += 64) acc[SLOT_L1] += fabsf(res[e].x) + fabsf(res[e].y);
   }
   if constexpr (MODE == ROW_R2C) {
-    const float* in = p.real_in + ch * p.real_cs + (long long)row * n;
-    for (int k = lane; k < M; k += 64) res[k] = *reinterpret_cast<const float2*>(in + 2 * k);
+    for (int c = 0; c < RW; ++c) {
+      const float* in = p.real_in + ch * p.real_cs + (long long)(row0 + c) * n;
+      for (int k = lane; k < M; k += 64) res[k * RW + c] = *reinterpret_cast<const float2*>(in + 2 * k);
+    }
   }
   if constexpr (MODE == ROW_SOLVE || MODE == ROW_PRIME) {
-    typename S::T* g = reinterpret_cast<typename S::T*>(p.g) + (long long)ch * n * n + (long long)row * n;
     const float th = p.fw.thr[j];
-    for (int k = lane; k < M; k += 64) {
-      float g0, g1;
-      S::unpack(S::load_pair(g + 2 * k), g0, g1);
-      const float b0v = fminf(fmaxf(g0, -th), th), b1v = fminf(fmaxf(g1, -th), th);
-      float n0 = g0, n1 = g1;
-      if constexpr (MODE == ROW_SOLVE) {
-        const float2 c = res[k];
-        n0 = S::round(b0v + c.x);
-        n1 = S::round(b1v + c.y);
-        S::store2(g + 2 * k, n0, n1);
+    for (int c = 0; c < RW; ++c) {
+      typename S::T* g = reinterpret_cast<typename S::T*>(p.g) + (long long)ch * n * n + (long long)(row0 + c) * n;
+      for (int k = lane; k < M; k += 64) {
+        float g0, g1;
+        S::unpack(S::load_pair(g + 2 * k), g0, g1);
+        const float b0v = fminf(fmaxf(g0, -th), th), b1v = fminf(fmaxf(g1, -th), th);
+        float n0 = g0, n1 = g1;
+        if constexpr (MODE == ROW_SOLVE) {
+          const float2 cc = res[k * RW + c];
+          n0 = S::round(b0v + cc.x);
+          n1 = S::round(b1v + cc.y);
+          S::store2(g + 2 * k, n0, n1);
+        }
+        const float nb0 = fminf(fmaxf(n0, -th), th), nb1 = fminf(fmaxf(n1, -th), th);
+        if constexpr (STATS && MODE == ROW_SOLVE) {
+          const float dv0 = (n0 - nb0) - (g0 - b0v), dv1 = (n1 - nb1) - (g1 - b1v);
+          const float db0 = nb0 - b0v, db1 = nb1 - b1v;
+          acc[SLOT_DY2] += dv0 * dv0 + dv1 * dv1;
+          acc[SLOT_DB2] += db0 * db0 + db1 * db1;
+          acc[SLOT_L1] += fabsf(n0 - nb0) + fabsf(n1 - nb1);
+        }
+        res[k * RW + c] = make_float2(n0 - 2.f * nb0, n1 - 2.f * nb1);
       }
-      const float nb0 = fminf(fmaxf(n0, -th), th), nb1 = fminf(fmaxf(n1, -th), th);
-      if constexpr (STATS && MODE == ROW_SOLVE) {
-        const float dv0 = (n0 - nb0) - (g0 - b0v), dv1 = (n1 - nb1) - (g1 - b1v);
-        const float db0 = nb0 - b0v, db1 = nb1 - b1v;
-        acc[SLOT_DY2] += dv0 * dv0 + dv1 * dv1;
-        acc[SLOT_DB2] += db0 * db0 + db1 * db1;
-        acc[SLOT_L1] += fabsf(n0 - nb0) + fabsf(n1 - nb1);
-      }
-      res[k] = make_float2(n0 - 2.f * nb0, n1 - 2.f * nb1);
     }
   }
   if constexpr (MODE == ROW_SHRINK) {
     const float th = p.fw.thr[j];
-    for (int k = lane; k < M; k += 64) {
-      const float2 c = res[k];
-      res[k] = make_float2(c.x - fminf(fmaxf(c.x, -th), th), c.y - fminf(fmaxf(c.y, -th), th));
+    for (int e = lane; e < M * RW; e += 64) {
+      const float2 c = res[e];
+      res[e] = make_float2(c.x - fminf(fmaxf(c.x, -th), th), c.y - fminf(fmaxf(c.y, -th), th));
     }
   }
   if constexpr (MODE == ROW_R2C || MODE == ROW_PRIME || MODE == ROW_SOLVE || MODE == ROW_SHRINK) {
@@ -222,19 +241,20 @@ __global__ __launch_bounds__(256) void k_row_g(RowParams p, GenParams gp) {
     if (emit) {
       fft_sync<SYNC_WAVE>();
       float2* other = res == b0 ? b1 : b0;
-      float2* Y = gfft<false, SYNC_WAVE>(res, other, gp.prow, 1, 64, lane, p.tw, 2);
+      float2* Y = gfft<false, SYNC_WAVE, RW>(res, other, gp.prow, 64, lane, p.tw, 2);
       int cb, pitch;
       long long off;
       plane_geom(p.lout, ch % p.lout.nf, cb, pitch, off);
-      float2* X = p.spec_out + (ch / p.lout.nf) * p.lout.ls + off;
-      for (int k = lane; k <= M; k += 64) {
-        const unsigned ip = unsigned(k - cb);
-        if (ip < unsigned(pitch)) {
-          const cpx yk = ld(Y + (k == M ? 0 : k));
-          const cpx ym = conj(ld(Y + (k == 0 ? 0 : M - k)));
+      const PlaneBuf B(p.spec_out + (ch / p.lout.nf) * p.lout.ls + off, pitch * n);
+      for (int c = 0; c < RW; ++c) {
+        const int row = row0 + c;
+        for (int k = lane; k <= M; k += 64) {
+          // stores of bins outside the plane's columns are dropped (out-of-range buffer stores)
+          const cpx yk = ld(Y + (k == M ? 0 : k) * RW + c);
+          const cpx ym = conj(ld(Y + (k == 0 ? 0 : M - k) * RW + c));
           const cpx s = yk + ym, d = yk - ym;
           const cpx w = ld(p.tw + k);
-          st(X + tix_rt(int(ip), row, n), (s - mul_i(cmul(d, w))) * 0.5f);
+          B.store(tix_g(k - cb, row, n), (s - mul_i(cmul(d, w))) * 0.5f);
         }
       }
     }
@@ -259,6 +279,17 @@ __device__ __forceinline__ float psi_at_rt(const ColParams& p, int4 win, int k0,
   return rel < win.y ? p.psiw[win.z + rel] : 0.f;
 }
 
+// The item's filter windows and plane geometry in LDS (as stage_item of the fixed sizes).
+__device__ __forceinline__ void stage_item_g(const ColParams& p, int4 it, int M, ItemStage<kGW>& st) {
+  for (int e = threadIdx.x; e < it.z * kGW; e += 256) {
+    const int i = e / kGW, cc = e % kGW;
+    const int j = p.flist[it.y + i];
+    const int k1 = it.x * kGW + cc;
+    st.win[i][cc] = k1 <= M ? p.pwin[j * (M + 1) + k1] : make_int4(0, 0, 0, 0);
+    if (cc == 0) st.geo[i] = p.tl.tab[j];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_colg_fwd(ColParams p, GenParams gp) {
   extern __shared__ float2 gsm[];
   const int n = gp.n, E = n * kGW;
@@ -267,7 +298,7 @@ __global__ __launch_bounds__(256) void k_colg_fwd(ColParams p, GenParams gp) {
   const long long strip = blockIdx.y * (long long)n * p.P + (long long)blockIdx.x * E;
   for (int e = threadIdx.x; e < E; e += 256) b0[e] = p.in[strip + e];
   __syncthreads();
-  float2* r = gfft<false, SYNC_BLOCK>(b0, b1, gp.pcol, kGW, 256, threadIdx.x, p.tw, 1);
+  float2* r = gfft<false, SYNC_BLOCK, kGW>(b0, b1, gp.pcol, 256, threadIdx.x, p.tw, 1);
   const int M = n / 2;
   for (int e = threadIdx.x; e < E; e += 256)
     if (blockIdx.x * kGW + (e % kGW) <= M) p.out[strip + e] = r[e];
@@ -279,25 +310,22 @@ __global__ __launch_bounds__(256) void k_colg_syn(ColParams p, GenParams gp) {
   float2* bu = gsm;
   float2* b0 = gsm + E;
   float2* b1 = gsm + 2 * E;
+  __shared__ ItemStage<kGW> stg;
   const int4 it = p.items[blockIdx.x];
   const int l = blockIdx.y;
+  stage_item_g(p, it, M, stg);
   const float2* U = p.in + l * (long long)n * p.P + (long long)it.x * E;
   for (int e = threadIdx.x; e < E; e += 256) bu[e] = U[e];
   __syncthreads();
   for (int i = 0; i < it.z; ++i) {
-    const int j = p.flist[it.y + i];
     for (int e = threadIdx.x; e < E; e += 256) {
-      const int c = e % kGW, k0 = e / kGW, k1 = it.x * kGW + c;
-      float f = 0.f;
-      if (k1 <= M) f = psi_at_rt(p, p.pwin[j * (M + 1) + k1], k0, n);
+      const float f = psi_at_rt(p, stg.win[i][e % kGW], e / kGW, n);   // zero window past N/2
       b0[e] = make_float2(bu[e].x * f * p.inv_n2, bu[e].y * f * p.inv_n2);
     }
     __syncthreads();
-    float2* r = gfft<true, SYNC_BLOCK>(b0, b1, gp.pcol, kGW, 256, threadIdx.x, p.tw, 1);
-    int cb, pitch;
-    long long off;
-    plane_geom(p.tl, j, cb, pitch, off);
-    float2* o = p.out + l * p.tl.ls + off + (long long)(it.x - cb / kGW) * E;
+    float2* r = gfft<true, SYNC_BLOCK, kGW>(b0, b1, gp.pcol, 256, threadIdx.x, p.tw, 1);
+    const int4 geo = stg.geo[i];
+    float2* o = p.out + l * p.tl.ls + geo_off(geo) + (long long)(it.x - geo.x / kGW) * E;
     for (int e = threadIdx.x; e < E; e += 256)
       if (it.x * kGW + (e % kGW) <= M) o[e] = r[e];
     __syncthreads();
@@ -308,7 +336,7 @@ __device__ void colg_finish(const ColParams& p, const GenParams& gp, float2* acc
   const int n = gp.n, E = n * kGW, M = n / 2;
   for (int e = threadIdx.x; e < E; e += 256) acc[e] = make_float2(acc[e].x * p.inv_n2, acc[e].y * p.inv_n2);
   __syncthreads();
-  float2* r = gfft<true, SYNC_BLOCK>(acc, b1, gp.pcol, kGW, 256, threadIdx.x, p.tw, 1);
+  float2* r = gfft<true, SYNC_BLOCK, kGW>(acc, b1, gp.pcol, 256, threadIdx.x, p.tw, 1);
   float2* o = p.out + l * (long long)n * p.P + (long long)strip * E;
   for (int e = threadIdx.x; e < E; e += 256)
     if (strip * kGW + (e % kGW) <= M) o[e] = r[e];
@@ -320,25 +348,23 @@ __global__ __launch_bounds__(256) void k_colg_ana(ColParams p, GenParams gp) {
   float2* ba = gsm;
   float2* b0 = gsm + E;
   float2* b1 = gsm + 2 * E;
+  __shared__ ItemStage<kGW> stg;
   const int4 it = p.items[blockIdx.x];
   const int l = blockIdx.y;
+  stage_item_g(p, it, M, stg);
   for (int e = threadIdx.x; e < E; e += 256) ba[e] = make_float2(0.f, 0.f);
+  __syncthreads();
   for (int i = 0; i < it.z; ++i) {
-    const int j = p.flist[it.y + i];
-    int cb, pitch;
-    long long off;
-    plane_geom(p.tl, j, cb, pitch, off);
-    const float2* in = p.in + l * p.tl.ls + off + (long long)(it.x - cb / kGW) * E;
+    const int4 geo = stg.geo[i];
+    const float2* in = p.in + l * p.tl.ls + geo_off(geo) + (long long)(it.x - geo.x / kGW) * E;
     for (int e = threadIdx.x; e < E; e += 256) {
       const int k1 = it.x * kGW + (e % kGW);
       b0[e] = k1 <= M ? in[e] : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    float2* r = gfft<false, SYNC_BLOCK>(b0, b1, gp.pcol, kGW, 256, threadIdx.x, p.tw, 1);
+    float2* r = gfft<false, SYNC_BLOCK, kGW>(b0, b1, gp.pcol, 256, threadIdx.x, p.tw, 1);
     for (int e = threadIdx.x; e < E; e += 256) {
-      const int c = e % kGW, k0 = e / kGW, k1 = it.x * kGW + c;
-      float f = 0.f;
-      if (k1 <= M) f = psi_at_rt(p, p.pwin[j * (M + 1) + k1], k0, n);
+      const float f = psi_at_rt(p, stg.win[i][e % kGW], e / kGW, n);   // zero window past N/2
       ba[e] = make_float2(ba[e].x + r[e].x * f, ba[e].y + r[e].y * f);
     }
     __syncthreads();

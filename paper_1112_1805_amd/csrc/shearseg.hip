@@ -22,6 +22,7 @@ struct shs_plan {
   int n, C, q, J, store, eta, M, P, PP, W, NS, device;
   int generic;         // 1: mixed-radix path (N not a power of two)
   int rpb;             // rows per row-pass block
+  int rw;              // generic path: rows per wave of the row pass (1, 2 or 4)
   FftPlan prow, pcol;  // mixed-radix stage lists (generic path)
   float* psi;          // [eta][N][PP] dense filter bank (half spectrum)
   float2* tw;          // [N] exp(-2 pi i m / N)
@@ -225,9 +226,14 @@ struct GenPipe {
   static GenParams gp(const shs_plan* p) { return GenParams{p->prow, p->pcol, p->n}; }
   template <int MODE, int ST, bool STATS>
   static void row_t(const shs_plan* p, const RowParams& rp, int channels, hipStream_t s) {
-    const dim3 grid(p->n / kGRows, channels);
-    const size_t lds = size_t(kGRows) * 2 * p->M * sizeof(float2);
-    hipLaunchKernelGGL((k_row_g<MODE, ST, STATS>), grid, dim3(256), lds, s, rp, gp(p));
+    // 4 waves per block, p->rw rows per wave
+    const dim3 grid(p->n / p->rpb, channels);
+    const size_t lds = size_t(4) * 2 * p->M * p->rw * sizeof(float2);
+    switch (p->rw) {
+      case 4: hipLaunchKernelGGL((k_row_g<MODE, ST, STATS, 4>), grid, dim3(256), lds, s, rp, gp(p)); break;
+      case 2: hipLaunchKernelGGL((k_row_g<MODE, ST, STATS, 2>), grid, dim3(256), lds, s, rp, gp(p)); break;
+      default: hipLaunchKernelGGL((k_row_g<MODE, ST, STATS, 1>), grid, dim3(256), lds, s, rp, gp(p)); break;
+    }
   }
   static void row(const shs_plan* p, int mode, int store, bool stats, const RowParams& rp, int channels,
                   hipStream_t s) {
@@ -284,7 +290,17 @@ bool make_fft_plan(int L, FftPlan& pl) {
   if (m == 2 || m == 4 || m == 8) { rs.insert(rs.begin(), m); m = 1; }
   if (m != 1 || int(rs.size()) > kMaxStages) return false;
   pl.ns = int(rs.size());
-  for (int i = 0; i < pl.ns; ++i) pl.radix[i] = rs[i];
+  int ns = 1;
+  for (int i = 0; i < pl.ns; ++i) {
+    pl.radix[i] = rs[i];
+    // x / ns = (umulhi(x, mag) + x) >> sh with sh = ceil(log2 ns), mag = floor(2^32 (2^sh - ns) / ns) + 1;
+    // exact for every ns <= 2048 and x < 2^21 (x < L * strip width here)
+    int sh = 0;
+    while ((1 << sh) < ns) ++sh;
+    pl.sh[i] = sh;
+    pl.mag[i] = ns == 1 ? 0u : unsigned((((unsigned long long)1 << 32) * ((1ull << sh) - ns)) / ns + 1);
+    ns *= rs[i];
+  }
   return true;
 }
 
@@ -795,7 +811,10 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
   p->prow = prow;
   p->pcol = pcol;
   p->W = pow2 ? by_size<WOf>(n) : kGW;
-  p->rpb = pow2 ? by_size<RpbOf>(n) : kGRows;
+  // generic rows: several rows per wave keep the lanes busy in stages with few butterflies;
+  // the two LDS buffers of a block (4 waves, 64 M rw bytes) stay at or below 48 KB
+  p->rw = pow2 ? 1 : (n % 16 == 0 && p->M <= 192) ? 4 : (p->M <= 384 ? 2 : 1);
+  p->rpb = pow2 ? by_size<RpbOf>(n) : 4 * p->rw;
   p->NS = p->M / p->W + 1;
   p->P = p->NS * p->W;  // columns of a dense spectrum plane (strip tiled); columns M+1.. unused
   p->PP = p->M + 16;    // row pitch of the dense filter bank
