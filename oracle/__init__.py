@@ -4,8 +4,9 @@ TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, obviously-correct
 restatement of what Haeuser & Steidl, "Convex Multiclass Segmentation with
 Shearlet Regularization" (arXiv 1112.1805) compute: the Meyer-type building
 blocks and the cone-adapted, translation-invariant finite discrete shearlet
-transform of Section 2, and the convex multi-label model and its ADMM of
-Section 3.  Everything is float64 numpy / scipy.fft, with no blocking, fusion
+transform of Section 2, the convex multi-label model and its ADMM of Section 3, and
+the primal-dual iteration the paper names as the alternative at the end of Section 3.
+Everything is float64 numpy / scipy.fft, with no blocking, fusion
 or reordering beyond what the paper's definitions state.
 
 Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
@@ -34,6 +35,7 @@ from .filters import freq_index, filter_list, num_filters, filter_bank, filter_s
 from .transform import fft2, ifft2, naive_dft2, forward, adjoint, denoise
 from .prox import soft_shrink, project_simplex, project_simplex_paper, project_simplex_bruteforce
 from .model import datacost, lambda_per_filter, admm, energy, labels_of, AdmmResult
+from .primaldual import primal_dual, dual_value, PdResult
 
 __all__ = [
     "meyer_v", "meyer_b", "psi1_hat", "psi2_hat", "phi_1d",
@@ -41,4 +43,5 @@ __all__ = [
     "fft2", "ifft2", "naive_dft2", "forward", "adjoint", "denoise",
     "soft_shrink", "project_simplex", "project_simplex_paper", "project_simplex_bruteforce",
     "datacost", "lambda_per_filter", "admm", "energy", "labels_of", "AdmmResult",
+    "primal_dual", "dual_value", "PdResult",
 ]
