@@ -266,6 +266,84 @@ def run_denoise(args):
     print(json.dumps(out_json), flush=True)
 
 
+def run_pd(args):
+    """The C2 workload solved by the primal-dual iteration (shs_solve_pd) instead of the
+    ADMM: same functional, same data, 300 iterations, steps tau = 2, sigma = 0.5."""
+    import torch
+    import paper_1112_1805_amd as pkg
+    from synth import make_c2
+    w = make_c2()
+    iters = args.iters if args.iters is not None else w.iters
+    tau, sigma = 2.0, 0.5
+    store = args.store
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    plan = pkg.Plan(w.n, w.channels, w.q, w.J, store, 0)
+    ws = plan.new_workspace()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    img = torch.tensor(w.img, dtype=torch.float32, device=dev)
+    s = torch.empty((w.q, w.n, w.n), dtype=torch.float32, device=dev)
+    u = torch.empty_like(s)
+    labels = torch.empty((w.n, w.n), dtype=torch.int32, device=dev)
+    hist = torch.empty((iters, 4), dtype=torch.float64, device=dev)
+
+    def step():
+        plan.datacost(img, w.codebook, s)
+        return plan.solve_pd(s, ws, w.lam, tau, sigma, iters, u=u, labels=labels, hist=hist)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done (pd)")
+    pkg.shs_profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = pkg.shs_profile_end()
+    its = args.steps * iters / dt
+    eta = plan.eta
+    sb = {"f32": 4, "bf16": 2, "f16": 2}[store]
+    n_launch, tot_ms = prof["row_pd"]
+    avg_s = tot_ms / n_launch / 1e3
+    amount = 2.0 * sb * eta * w.q * w.n * w.n          # dual variable read + written once
+    roofline = {"bound": "hbm", "achieved": round(amount / avg_s / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(amount / avg_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "row_pd",
+                "algorithmic_per_launch": amount, "avg_launch_ms": round(avg_s * 1e3, 5)}
+    out = {
+        "metric": "primal-dual iters/s and Mpixel·label·filter/s at 1024^2 K=5 J=4",
+        "value": round(its, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{describe(w, store, iters)}; solver: primal-dual (Chambolle-Pock), "
+                               f"tau={tau}, sigma={sigma}", "iters_per_step": iters, "state_storage": store},
+        "mpixel_label_filter_per_s": round(its * w.n * w.n * w.q * eta / 1e6, 1),
+        "ms_per_iter": round(dt / args.steps / iters * 1e3, 4),
+        "roofline": roofline,
+        "kernel_breakdown_ms": {k: {"launches": v[0], "total_ms": round(v[1], 4), "avg_ms": round(v[1] / v[0], 5)}
+                                for k, v in prof.items()},
+        "final_stats": {k: (round(v, 9) if isinstance(v, float) else v) for k, v in st.items()},
+        "plan_create_ms": round(plan_ms, 2),
+        "source_hash": source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        workers = min(16, os.cpu_count() or 1)
+        os.environ["ORACLE_FFT_WORKERS"] = str(workers)
+        import oracle
+        oracle.transform.WORKERS = workers
+        s64 = oracle.datacost(np.float32(w.img).astype(np.float64), np.float32(w.codebook).astype(np.float64))
+        B = oracle.filter_bank(w.n, w.J)
+        lam_f = oracle.lambda_per_filter(w.lam, w.J)
+        t0 = time.perf_counter()
+        oracle.primal_dual(s64, B, lam_f, tau, sigma, 1)
+        cdt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(1.0 / cdt, 6), "unit": "iters/s", "cores": workers, "kind": "oracle",
+                               "sample": f"1 primal-dual iteration of the same workload, FP64 oracle "
+                                         f"({workers} scipy.fft workers); {cdt:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def kernel_units(w, iters, eta, store_bytes):
     """Algorithmic bytes / flops per launch of each kernel class (one launch per iteration)."""
     n, q = w.n, w.q
@@ -290,7 +368,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3", "c4", "denoise"])
+    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3", "c4", "denoise", "pd"])
     ap.add_argument("--store", default=None, choices=["f32", "bf16", "f16"],
                     help="state storage (default f16 for c0-c2/c4, f32 for the c3 batch)")
     ap.add_argument("--iters", type=int, default=None, help="ADMM iterations per step (default: workload's)")
@@ -320,6 +398,9 @@ def main():
         return
     if args.workload == "denoise":
         run_denoise(args)
+        return
+    if args.workload == "pd":
+        run_pd(args)
         return
     w = workload(args.workload)
     iters = args.iters if args.iters is not None else w.iters

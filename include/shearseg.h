@@ -165,6 +165,32 @@ shs_status shs_solve(const shs_plan* plan, const shs_params* params, const float
                      size_t ws_bytes, float* d_u, int32_t* d_labels, double* d_hist, shs_stats* h_stats,
                      void* stream);
 
+/* Parameters of the primal-dual solver.  lambda/lambda_len as in shs_params (the weights
+ * of the regulariser, low-pass first); tau (primal) and sigma (dual) step sizes, finite,
+ * > 0, tau * sigma <= 1 (the operator I_q (x) S has norm 1 by Theorem 2.2). */
+typedef struct {
+  const float* lambda;   /* HOST */
+  int32_t lambda_len;
+  float tau, sigma;
+  int32_t iters;         /* >= 0 (0 returns the zero start) */
+} shs_pd_params;
+
+/* Primal-dual (Chambolle-Pock) solver for the same functional as shs_solve, the
+ * alternative the paper names at the end of Section 3: from u = ubar = y = 0,
+ *   y    = clip(y + sigma S ubar, +-lambda_j)          (per label and filter)
+ *   u'   = P_C(u - tau (S^T y + s)),   ubar = 2 u' - u,   u = u'
+ * The dual variable y takes the place of the ADMM state (same workspace, same storage
+ * type); the dual step is fused into the row pass between the transform's column passes.
+ * Outputs as shs_solve with u^K in place of w^K (it lies in C).  d_hist: NULL or float64
+ * [iters][4] = (||u' - u||, ||y' - y||, ||u' - u||^2 + ||y' - y||^2,
+ * <u', s> + sum_j lambda_j ||(S ubar)_j||_1) per iteration.  h_stats: as shs_solve
+ * (r_primal = ||u' - u||, r_dual = ||y' - y|| of the last iteration, exact energy of u^K).
+ * Errors: SHS_E_INVALID (bad steps or lambda), SHS_E_WORKSPACE, SHS_E_DEVICE,
+ * SHS_E_NUMERIC (non-finite value seen by the last iteration's reduction). */
+shs_status shs_solve_pd(const shs_plan* plan, const shs_pd_params* params, const float* d_s, void* d_ws,
+                        size_t ws_bytes, float* d_u, int32_t* d_labels, double* d_hist, shs_stats* h_stats,
+                        void* stream);
+
 /* Energy F(u) = <u, s> + sum_l sum_j lambda_j ||S_j u_l||_1 of (problemSegmentation) for a
  * given u (float32 [q][N][N]; the indicator term is not evaluated).  Uses params->lambda /
  * lambda_len only.  Synchronises the stream; result in *h_energy (FP64 accumulation). */

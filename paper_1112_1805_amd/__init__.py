@@ -33,6 +33,11 @@ class ShsParams(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("resume", ctypes.c_int32)]
 
 
+class ShsPdParams(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.POINTER(ctypes.c_float)), ("lambda_len", ctypes.c_int32),
+                ("tau", ctypes.c_float), ("sigma", ctypes.c_float), ("iters", ctypes.c_int32)]
+
+
 class ShsStats(ctypes.Structure):
     _fields_ = [("iters_done", ctypes.c_int32), ("energy", ctypes.c_double),
                 ("energy_surrogate", ctypes.c_double), ("r_primal", ctypes.c_double),
@@ -67,6 +72,8 @@ _SIGS = {
     "shs_shearlet_denoise": (_I32, [_VP, _I32, ctypes.POINTER(ctypes.c_float), _I32, _VP, _VP, _VP, _SZ, _VP]),
     "shs_solve": (_I32, [_VP, ctypes.POINTER(ShsParams), _VP, _VP, _SZ, _VP, _VP, _VP,
                          ctypes.POINTER(ShsStats), _VP]),
+    "shs_solve_pd": (_I32, [_VP, ctypes.POINTER(ShsPdParams), _VP, _VP, _SZ, _VP, _VP, _VP,
+                            ctypes.POINTER(ShsStats), _VP]),
     "shs_energy": (_I32, [_VP, ctypes.POINTER(ShsParams), _VP, _VP, _VP, _SZ,
                           ctypes.POINTER(ctypes.c_double), _VP]),
     "shs_batch_create": (_I32, [_I32, ctypes.POINTER(ShsShape), ctypes.c_int, ctypes.POINTER(_VP)]),
@@ -245,6 +252,30 @@ class Plan:
                                _ptr(labels), _ptr(hist), ctypes.byref(st) if want_stats else None,
                                _stream(stream)), "shs_solve")
         del keep
+        return st.as_dict() if want_stats else None
+
+    def solve_pd(self, s, ws, lam, tau, sigma, iters, u=None, labels=None, hist=None, want_stats=True,
+                 stream=None):
+        """Primal-dual solver (shs_solve_pd); same outputs as solve()."""
+        _expect(s, (self.q, self.n, self.n), "f32", "d_s")
+        if u is not None:
+            _expect(u, (self.q, self.n, self.n), "f32", "d_u")
+        if labels is not None:
+            _expect(labels, (self.n, self.n), "i32", "d_labels")
+        if hist is not None:
+            _expect(hist, (iters, 4), "f64", "d_hist")
+        arr = np.ascontiguousarray(np.asarray(lam, dtype=np.float32).ravel())
+        prm = ShsPdParams()
+        prm.lambda_ = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        prm.lambda_len = arr.size
+        prm.tau = float(tau)
+        prm.sigma = float(sigma)
+        prm.iters = int(iters)
+        st = ShsStats()
+        _check(lib().shs_solve_pd(self.handle, ctypes.byref(prm), _ptr(s), _ptr(ws), ws.numel(), _ptr(u),
+                                  _ptr(labels), _ptr(hist), ctypes.byref(st) if want_stats else None,
+                                  _stream(stream)), "shs_solve_pd")
+        del arr
         return st.as_dict() if want_stats else None
 
     def energy(self, s, u, ws, lam, stream=None) -> float:

@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_row_g(RowParams p, GenParams gp) {
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   float2* res = b0;
 
-  if constexpr (MODE == ROW_SOLVE || MODE == ROW_C2R || MODE == ROW_ENERGY || MODE == ROW_SHRINK) {
+  if constexpr (MODE == ROW_SOLVE || MODE == ROW_C2R || MODE == ROW_ENERGY || MODE == ROW_SHRINK || MODE == ROW_PD) {
     int cb, pitch;
     long long off;
     plane_geom(p.lin, ch % p.lin.nf, cb, pitch, off);
@@ -228,6 +228,26 @@ __global__ __launch_bounds__(256) void k_row_g(RowParams p, GenParams gp) {
       }
     }
   }
+  if constexpr (MODE == ROW_PD) {
+    const float th = p.fw.thr[j];
+    for (int c = 0; c < RW; ++c) {
+      typename S::T* g = reinterpret_cast<typename S::T*>(p.g) + (long long)ch * n * n + (long long)(row0 + c) * n;
+      for (int k = lane; k < M; k += 64) {
+        float y0, y1;
+        S::unpack(S::load_pair(g + 2 * k), y0, y1);
+        const float2 cc = res[k * RW + c];
+        const float n0 = S::round(fminf(fmaxf(fmaf(p.sigma, cc.x, y0), -th), th));
+        const float n1 = S::round(fminf(fmaxf(fmaf(p.sigma, cc.y, y1), -th), th));
+        S::store2(g + 2 * k, n0, n1);
+        if constexpr (STATS) {
+          const float d0 = n0 - y0, d1 = n1 - y1;
+          acc[SLOT_DY2] += d0 * d0 + d1 * d1;
+          acc[SLOT_L1] += fabsf(cc.x) + fabsf(cc.y);
+        }
+        res[k * RW + c] = make_float2(n0, n1);
+      }
+    }
+  }
   if constexpr (MODE == ROW_SHRINK) {
     const float th = p.fw.thr[j];
     for (int e = lane; e < M * RW; e += 64) {
@@ -235,7 +255,7 @@ __global__ __launch_bounds__(256) void k_row_g(RowParams p, GenParams gp) {
       res[e] = make_float2(c.x - fminf(fmaxf(c.x, -th), th), c.y - fminf(fmaxf(c.y, -th), th));
     }
   }
-  if constexpr (MODE == ROW_R2C || MODE == ROW_PRIME || MODE == ROW_SOLVE || MODE == ROW_SHRINK) {
+  if constexpr (MODE == ROW_R2C || MODE == ROW_PRIME || MODE == ROW_SOLVE || MODE == ROW_SHRINK || MODE == ROW_PD) {
     bool emit = true;
     if constexpr (MODE == ROW_SOLVE) emit = p.emit != 0;
     if (emit) {

@@ -271,7 +271,7 @@ struct PlaneBuf {
 };
 
 // ---------------------------------------------------------------- row pass
-enum RowMode { ROW_SOLVE = 0, ROW_C2R = 1, ROW_R2C = 2, ROW_PRIME = 3, ROW_ENERGY = 4, ROW_SHRINK = 5 };
+enum RowMode { ROW_SOLVE = 0, ROW_C2R = 1, ROW_R2C = 2, ROW_PRIME = 3, ROW_ENERGY = 4, ROW_SHRINK = 5, ROW_PD = 6 };
 
 // Row FFTs have complex length M = N/2: (R, RM) with R * R * RM = M.
 template <int M> struct RowFft;
@@ -335,6 +335,7 @@ struct RowParams {
   long long real_cs;       // channel stride of real rows (floats)
   int eta;                 // filters per label: filter of channel ch is ch % eta
   int emit;                // SOLVE: write the next adjoint input spectrum
+  float sigma;             // PD: dual step size
   FilterWeights fw;        // passed by value (kernel argument memory)
 };
 
@@ -424,14 +425,14 @@ __global__ __launch_bounds__(256) void k_row(RowParams p) {
   float acc[4] = {0.f, 0.f, 0.f, 0.f};   // per-thread partial sums of one row segment
   typename S::T* gp = nullptr;
   typename S::Pair gv[G::R];
-  if constexpr (MODE == ROW_SOLVE || MODE == ROW_PRIME) {
+  if constexpr (MODE == ROW_SOLVE || MODE == ROW_PRIME || MODE == ROW_PD) {
     // The state does not depend on the inverse FFT below: load it first so its latency
     // overlaps the FFT.
     gp = reinterpret_cast<typename S::T*>(p.g) + (long long)ch * N * N + (long long)row * N;
     static_for<G::R>([&](auto r) { gv[r] = S::load_pair(gp + 2 * (t + r * G::T)); });
   }
 
-  if constexpr (MODE == ROW_SOLVE || MODE == ROW_C2R || MODE == ROW_ENERGY || MODE == ROW_SHRINK) {
+  if constexpr (MODE == ROW_SOLVE || MODE == ROW_C2R || MODE == ROW_ENERGY || MODE == ROW_SHRINK || MODE == ROW_PD) {
     int cb, pitch;
     long long off;
     const int f = ch % p.lin.nf;
@@ -488,6 +489,24 @@ __global__ __launch_bounds__(256) void k_row(RowParams p) {
     // term live, doubling the register footprint.
     if constexpr (STATS && MODE == ROW_SOLVE) __asm__ volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[3]));
   }
+  if constexpr (MODE == ROW_PD) {
+    // dual step of the primal-dual iteration: y <- clip(y + sigma c, +-lambda_j), c = (K ubar)_j
+    const float th = p.fw.thr[j];
+    static_for<G::R>([&](auto r) {
+      float y0, y1;
+      S::unpack(gv[r], y0, y1);
+      const float n0 = S::round(fminf(fmaxf(fmaf(p.sigma, a[r].x, y0), -th), th));
+      const float n1 = S::round(fminf(fmaxf(fmaf(p.sigma, a[r].y, y1), -th), th));
+      S::store2(gp + 2 * (t + r * G::T), n0, n1);
+      if constexpr (STATS) {
+        const float d0 = n0 - y0, d1 = n1 - y1;
+        acc[SLOT_DY2] += d0 * d0 + d1 * d1;
+        acc[SLOT_L1] += fabsf(a[r].x) + fabsf(a[r].y);
+      }
+      a[r] = cpx{n0, n1};
+    });
+    if constexpr (STATS) __asm__ volatile("" : "+v"(acc[0]), "+v"(acc[3]));
+  }
   if constexpr (MODE == ROW_SHRINK) {
     // soft shrinkage of the coefficient row (Section 3's S_lambda, threshold thr_j)
     const float th = p.fw.thr[j];
@@ -495,7 +514,7 @@ __global__ __launch_bounds__(256) void k_row(RowParams p) {
       a[r] = cpx{a[r].x - fminf(fmaxf(a[r].x, -th), th), a[r].y - fminf(fmaxf(a[r].y, -th), th)};
     });
   }
-  if constexpr (MODE == ROW_R2C || MODE == ROW_PRIME || MODE == ROW_SOLVE || MODE == ROW_SHRINK) {
+  if constexpr (MODE == ROW_R2C || MODE == ROW_PRIME || MODE == ROW_SOLVE || MODE == ROW_SHRINK || MODE == ROW_PD) {
     bool emit = true;
     if constexpr (MODE == ROW_SOLVE) emit = p.emit != 0;
     if (emit) {
@@ -775,10 +794,35 @@ struct PixParams {
   int q;
 };
 
+// Projection of one label vector onto the simplex C, in place: the paper's procedure
+// (project onto the hyperplane sum = 1, drop the entries that are not positive,
+// re-project the rest, until none is dropped; at most q rounds).
+template <int MQ>
+__device__ __forceinline__ void simplex_project(float (&g)[MQ], int q) {
+  bool act[MQ];
+  int cnt = q;
+#pragma unroll
+  for (int l = 0; l < MQ; ++l) act[l] = l < q;
+  float tau = 0.f;
+  for (int round = 0; round < MQ; ++round) {
+    float sum = 0.f;
+#pragma unroll
+    for (int l = 0; l < MQ; ++l) sum += act[l] ? g[l] : 0.f;
+    tau = (sum - 1.f) / float(cnt);
+    bool dropped = false;
+#pragma unroll
+    for (int l = 0; l < MQ; ++l) {
+      if (act[l] && g[l] - tau <= 0.f) { act[l] = false; --cnt; dropped = true; }
+    }
+    if (!dropped) break;
+  }
+  // a single remaining entry is the vertex: exactly 1 (g - (g - 1) need not round to 1)
+#pragma unroll
+  for (int l = 0; l < MQ; ++l) g[l] = act[l] ? (cnt == 1 ? 1.f : g[l] - tau) : 0.f;
+}
+
 // u = 1/2 [z + (w - b_w) - gamma s]  (Section 3 u-update, A^T A = 2I);
 // g_w = b_w + u;  w = P_C(g_w) (pixelwise simplex);  b_w = g_w - w.
-// The projection follows the paper's procedure: project onto the hyperplane sum = 1,
-// drop the entries that are not positive, re-project the rest, until none is dropped.
 template <bool STATS, bool HAVE_Z>
 __global__ __launch_bounds__(256) void k_pixel(PixParams p) {
   constexpr int MQ = 8;
@@ -787,9 +831,10 @@ __global__ __launch_bounds__(256) void k_pixel(PixParams p) {
   const bool active = i < p.n2;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (active) {
-    float gw[MQ], wo[MQ], bo[MQ], sv[MQ];
+    float gw[MQ], wn[MQ], wo[MQ], bo[MQ], sv[MQ];
 #pragma unroll
     for (int l = 0; l < MQ; ++l) {
+      gw[l] = 0.f;
       if (l < p.q) {
         const long long o = l * p.n2 + i;
         const float z = HAVE_Z ? p.z[o] : 0.f;
@@ -798,37 +843,67 @@ __global__ __launch_bounds__(256) void k_pixel(PixParams p) {
         p.u[o] = u;
         gw[l] = bo[l] + u;
       }
+      wn[l] = gw[l];
     }
-    bool act[MQ];
-    int cnt = p.q;
-#pragma unroll
-    for (int l = 0; l < MQ; ++l) act[l] = l < p.q;
-    float tau = 0.f;
-    for (int round = 0; round < MQ; ++round) {
-      float sum = 0.f;
-#pragma unroll
-      for (int l = 0; l < MQ; ++l) sum += act[l] ? gw[l] : 0.f;
-      tau = (sum - 1.f) / float(cnt);
-      bool dropped = false;
-#pragma unroll
-      for (int l = 0; l < MQ; ++l) {
-        if (act[l] && gw[l] - tau <= 0.f) { act[l] = false; --cnt; dropped = true; }
-      }
-      if (!dropped) break;
-    }
+    simplex_project<MQ>(wn, p.q);
 #pragma unroll
     for (int l = 0; l < MQ; ++l) {
       if (l < p.q) {
         const long long o = l * p.n2 + i;
-        const float wn = act[l] ? gw[l] - tau : 0.f;
-        const float bn = gw[l] - wn;
-        p.w[o] = wn;
+        const float bn = gw[l] - wn[l];
+        p.w[o] = wn[l];
         p.bw[o] = bn;
         if constexpr (STATS) {
-          const float dw = wn - wo[l], db = bn - bo[l];
+          const float dw = wn[l] - wo[l], db = bn - bo[l];
           acc[SLOT_DY2] += double(dw) * dw;
           acc[SLOT_DB2] += double(db) * db;
-          acc[SLOT_WS] += double(wn) * double(sv[l]);
+          acc[SLOT_WS] += double(wn[l]) * double(sv[l]);
+        }
+      }
+    }
+  }
+  if constexpr (STATS) {
+    block_sum4<4>(acc, red);
+    if (threadIdx.x == 0) {
+      double* o = p.partials + (long long)blockIdx.x * 4;
+      o[0] = acc[0]; o[1] = acc[1]; o[2] = acc[2]; o[3] = acc[3];
+    }
+  }
+}
+
+// Primal step of the primal-dual iteration: u_new = P_C(u - tau (K^T y + s)) and the
+// extrapolation ubar = 2 u_new - u.  Here w holds u (read, written), u receives ubar, z
+// holds K^T y, gamma is the primal step tau.  Partials: ||u_new - u||^2, <u_new, s>.
+template <bool STATS>
+__global__ __launch_bounds__(256) void k_pixel_pd(PixParams p) {
+  constexpr int MQ = 8;
+  __shared__ double red[4 * 4];
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const bool active = i < p.n2;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (active) {
+    float un[MQ], uo[MQ], sv[MQ];
+#pragma unroll
+    for (int l = 0; l < MQ; ++l) {
+      un[l] = 0.f;
+      if (l < p.q) {
+        const long long o = l * p.n2 + i;
+        uo[l] = p.w[o];
+        sv[l] = p.s[o];
+        un[l] = uo[l] - p.gamma * (p.z[o] + sv[l]);
+      }
+    }
+    simplex_project<MQ>(un, p.q);
+#pragma unroll
+    for (int l = 0; l < MQ; ++l) {
+      if (l < p.q) {
+        const long long o = l * p.n2 + i;
+        p.w[o] = un[l];
+        p.u[o] = 2.f * un[l] - uo[l];
+        if constexpr (STATS) {
+          const float du = un[l] - uo[l];
+          acc[SLOT_DB2] += double(du) * du;
+          acc[SLOT_WS] += double(un[l]) * double(sv[l]);
         }
       }
     }

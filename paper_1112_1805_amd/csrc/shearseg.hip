@@ -80,11 +80,11 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // ---------------------------------------------------------------- kernel timing
 enum KClass {
   KC_ROW_SOLVE, KC_COL_SYN, KC_COL_ANA, KC_COL_FINAL, KC_COL_FWD, KC_ROW_C2R, KC_ROW_R2C, KC_ROW_PRIME,
-  KC_ROW_ENERGY, KC_PIXEL, KC_REDUCE, KC_OTHER, KC_BATCH, KC_ROW_SHRINK, KC_COUNT
+  KC_ROW_ENERGY, KC_PIXEL, KC_REDUCE, KC_OTHER, KC_BATCH, KC_ROW_SHRINK, KC_ROW_PD, KC_COUNT
 };
 const char* const kKClassName[KC_COUNT] = {"row_solve", "col_syn", "col_ana", "col_final", "col_fwd", "row_c2r",
                                            "row_r2c", "row_prime", "row_energy", "pixel", "reduce", "other",
-                                           "batch_solve", "row_shrink"};
+                                           "batch_solve", "row_shrink", "row_pd"};
 
 struct Prof {
   std::mutex mu;
@@ -207,6 +207,11 @@ struct Pipe {
       case ROW_R2C: row_t<ROW_R2C, ST_F32, false>(rp, channels, s); break;
       case ROW_ENERGY: row_t<ROW_ENERGY, ST_F32, true>(rp, channels, s); break;
       case ROW_SHRINK: row_t<ROW_SHRINK, ST_F32, false>(rp, channels, s); break;
+      case ROW_PD:
+        if (store == ST_F32) { stats ? row_t<ROW_PD, ST_F32, true>(rp, channels, s) : row_t<ROW_PD, ST_F32, false>(rp, channels, s); }
+        else if (store == ST_BF16) { stats ? row_t<ROW_PD, ST_BF16, true>(rp, channels, s) : row_t<ROW_PD, ST_BF16, false>(rp, channels, s); }
+        else { stats ? row_t<ROW_PD, ST_F16, true>(rp, channels, s) : row_t<ROW_PD, ST_F16, false>(rp, channels, s); }
+        break;
     }
   }
   static void col(const shs_plan*, int kind, const ColParams& cp, int nblocks, int labels, hipStream_t s) {
@@ -252,6 +257,11 @@ struct GenPipe {
       case ROW_R2C: row_t<ROW_R2C, ST_F32, false>(p, rp, channels, s); break;
       case ROW_ENERGY: row_t<ROW_ENERGY, ST_F32, true>(p, rp, channels, s); break;
       case ROW_SHRINK: row_t<ROW_SHRINK, ST_F32, false>(p, rp, channels, s); break;
+      case ROW_PD:
+        if (store == ST_F32) { stats ? row_t<ROW_PD, ST_F32, true>(p, rp, channels, s) : row_t<ROW_PD, ST_F32, false>(p, rp, channels, s); }
+        else if (store == ST_BF16) { stats ? row_t<ROW_PD, ST_BF16, true>(p, rp, channels, s) : row_t<ROW_PD, ST_BF16, false>(p, rp, channels, s); }
+        else { stats ? row_t<ROW_PD, ST_F16, true>(p, rp, channels, s) : row_t<ROW_PD, ST_F16, false>(p, rp, channels, s); }
+        break;
     }
   }
   static void col(const shs_plan* p, int kind, const ColParams& cp, int nblocks, int labels, hipStream_t s) {
@@ -331,6 +341,7 @@ int row_class(int mode) {
     case ROW_PRIME: return KC_ROW_PRIME;
     case ROW_ENERGY: return KC_ROW_ENERGY;
     case ROW_SHRINK: return KC_ROW_SHRINK;
+    case ROW_PD: return KC_ROW_PD;
   }
   return KC_OTHER;
 }
@@ -667,6 +678,49 @@ void enqueue_iteration(const Ctx& c, const float* d_s, float gamma, bool have_ad
   if (stats) enqueue_reduce(c, L.nrow_parts + npix_blocks, hist_row, gamma);
 }
 
+// One primal-dual iteration (Chambolle-Pock for the functional of Section 3):
+// K ubar (synthesis), the dual step fused into the row pass (y <- clip(y + sigma K ubar),
+// then the row FFT of y), K^T y (analysis), the primal step and extrapolation per pixel.
+void enqueue_pd_iteration(const Ctx& c, const float* d_s, float tau, float sigma, bool stats, double* hist_row) {
+  const shs_plan* p = c.p;
+  const Layout& L = c.L;
+  const int q = p->q;
+  const long long n2 = (long long)p->n * p->n;
+  const long long npix_blocks = (n2 + 255) / 256;
+  enqueue_synthesis(c, c.at<float>(L.us), q);
+  RowParams rp{};
+  rp.spec_in = c.at<float2>(L.t1);
+  rp.lin = pruned_layout(p);
+  rp.spec_out = c.at<float2>(L.t2);
+  rp.lout = pruned_layout(p);
+  rp.g = c.ws + L.g;
+  rp.emit = 1;
+  rp.sigma = sigma;
+  run_row(c, ROW_PD, p->store, stats, rp, q * p->eta);
+  enqueue_analysis(c, q);
+  RowParams rz{};
+  rz.spec_in = c.at<float2>(L.z);
+  rz.lin = dense_layout(p);
+  rz.real_out = c.at<float>(L.zs);
+  run_row(c, ROW_C2R, ST_F32, false, rz, q);
+  PixParams pp{};
+  pp.z = c.at<float>(L.zs);
+  pp.w = c.at<float>(L.w);
+  pp.s = d_s;
+  pp.u = c.at<float>(L.us);
+  pp.partials = c.at<double>(L.parts) + L.nrow_parts * 4;
+  pp.n2 = n2;
+  pp.gamma = tau;
+  pp.q = q;
+  {
+    Timed tm(c.s, KC_PIXEL);
+    const dim3 g{unsigned(npix_blocks)}, b{256};
+    if (stats) hipLaunchKernelGGL((k_pixel_pd<true>), g, b, 0, c.s, pp);
+    else hipLaunchKernelGGL((k_pixel_pd<false>), g, b, 0, c.s, pp);
+  }
+  if (stats) enqueue_reduce(c, L.nrow_parts + npix_blocks, hist_row, 1.0);
+}
+
 }  // namespace
 
 // A batch of images of different sizes and label counts (one plan per distinct shape).
@@ -890,6 +944,66 @@ shs_status shs_datacost(const shs_plan* p, const float* d_img, const float* h_co
   hipLaunchKernelGGL(k_datacost, dim3(unsigned((n2 + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
                      d_img, p->C, cb, p->q, pw, d_s, n2);
   LAUNCHCHK("datacost");
+  return SHS_OK;
+}
+
+shs_status shs_solve_pd(const shs_plan* p, const shs_pd_params* prm, const float* d_s, void* d_ws, size_t ws_bytes,
+                        float* d_u, int32_t* d_labels, double* d_hist, shs_stats* h_stats, void* stream) {
+  if (!p || !prm || !d_s) return fail(SHS_E_INVALID, "null argument");
+  if (!(prm->tau > 0.f) || !(prm->sigma > 0.f) || !std::isfinite(prm->tau) || !std::isfinite(prm->sigma))
+    return fail(SHS_E_INVALID, "tau and sigma must be finite and > 0");
+  if (double(prm->tau) * double(prm->sigma) > 1.0 + 1e-6)
+    return fail(SHS_E_INVALID, "tau * sigma must be <= 1 (||K|| = 1)");
+  if (prm->iters < 0) return fail(SHS_E_INVALID, "iters must be >= 0");
+  DeviceGuard dg(p->device);
+  Ctx c;
+  shs_status st = make_ctx(p, d_ws, ws_bytes, stream, c);
+  if (st != SHS_OK) return st;
+  shs_params lp{};
+  lp.lambda = prm->lambda;
+  lp.lambda_len = prm->lambda_len;
+  lp.gamma = 1.f;                        // thresholds = lambda_j (the dual box)
+  if ((st = set_lambda(c, &lp)) != SHS_OK) return st;
+  const long long n2 = (long long)p->n * p->n;
+  // zero start: y (in the g array), u (in w) and ubar
+  enqueue_zero_state(c);
+  {
+    const long long words = (long long)p->q * n2;
+    hipLaunchKernelGGL(k_fill_u32, dim3(unsigned((words + 255) / 256)), dim3(256), 0, c.s,
+                       reinterpret_cast<uint32_t*>(c.at<float>(c.L.us)), words, 0u);
+  }
+  LAUNCHCHK("initial state");
+  double tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  bool have = false;
+  for (int it = 0; it < prm->iters; ++it) {
+    const bool last = it == prm->iters - 1;
+    const bool stats = d_hist != nullptr || (last && h_stats != nullptr);
+    enqueue_pd_iteration(c, d_s, prm->tau, prm->sigma, stats, d_hist ? d_hist + 4LL * it : nullptr);
+    LAUNCHCHK("primal-dual iteration");
+    if (last && h_stats) {
+      HIPCHK(hipMemcpyAsync(tot, c.at<double>(c.L.sdev), 5 * 8, hipMemcpyDeviceToHost, c.s));
+      HIPCHK(hipStreamSynchronize(c.s));
+      have = true;
+      if (tot[4] != 0.0) return fail(SHS_E_NUMERIC, "non-finite value in the primal-dual iteration");
+    }
+  }
+  enqueue_epilogue(c, d_u, d_labels);
+  LAUNCHCHK("epilogue");
+  if (h_stats) {
+    shs_stats out{};
+    out.iters_done = prm->iters;
+    if (have) {
+      out.r_primal = std::sqrt(tot[SLOT_DB2]);
+      out.r_dual = std::sqrt(tot[SLOT_DY2]);
+      out.r_combined = tot[SLOT_DY2] + tot[SLOT_DB2];
+      out.energy_surrogate = tot[SLOT_WS] + tot[SLOT_L1];
+    }
+    double e = 0.0;
+    st = energy_of(c, c.at<float>(c.L.w), d_s, &e);
+    if (st != SHS_OK) return st;
+    out.energy = e;
+    *h_stats = out;
+  }
   return SHS_OK;
 }
 

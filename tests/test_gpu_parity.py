@@ -338,6 +338,92 @@ def test_c2_full_size_prefix(store, atol_u, e_rel):
     assert np.mean(g["labels"] == r.labels) >= 0.999
 
 
+# ------------------------------------------------------------------ primal-dual solver
+def run_gpu_pd(w, iters, tau, sigma, store="f32", lam=None, s=None):
+    pkg = _pkg()
+    n, q = w.n, w.q
+    plan = pkg.Plan(n, w.channels, q, w.J, store)
+    ws = plan.new_workspace()
+    if s is None:
+        s = torch.empty((q, n, n), dtype=torch.float32, device="cuda:0")
+        plan.datacost(dev_t(w.img), w.codebook, s)
+    u = torch.empty((q, n, n), dtype=torch.float32, device="cuda:0")
+    labels = torch.empty((n, n), dtype=torch.int32, device="cuda:0")
+    h = torch.zeros((iters, 4), dtype=torch.float64, device="cuda:0")
+    st = plan.solve_pd(s, ws, w.lam if lam is None else lam, tau, sigma, iters, u=u, labels=labels, hist=h)
+    torch.cuda.synchronize()
+    return dict(u=u.cpu().numpy(), labels=labels.cpu().numpy(), stats=st, hist=h.cpu().numpy(), s=s,
+                plan=plan, ws=ws)
+
+
+PD_CASES = [(64, 3, 2, 1, 30, 0.9, 0.9), (64, 1, 1, 1, 5, 1.0, 1.0), (128, 5, 3, 3, 20, 2.0, 0.5),
+            (96, 4, 2, 1, 20, 0.9, 0.9), (160, 2, 3, 1, 15, 1.0, 1.0), (256, 8, 4, 1, 10, 0.5, 2.0)]
+
+
+@pytest.mark.parametrize("n,q,J,C,iters,tau,sigma", PD_CASES)
+def test_primal_dual_matches_oracle(n, q, J, C, iters, tau, sigma):
+    w = make_small(n, q, J, channels=C, seed=3 * n + q, lam=0.15, iters=iters)
+    s = O.datacost(f32(w.img), f32(w.codebook))
+    B = O.filter_bank(n, J)
+    lam_f = O.lambda_per_filter(w.lam, J)
+    r = O.primal_dual(s, B, lam_f, tau, sigma, iters)
+    g = run_gpu_pd(w, iters, tau, sigma)
+    assert np.max(np.abs(g["u"] - r.u)) < 5e-5
+    assert np.mean(g["labels"] == r.labels) >= 0.999
+    # per-iteration history: ||du||, ||dy|| (relative to the sequence's size), surrogate
+    assert np.max(np.abs(g["hist"][:, 0] - r.du)) < 1e-4 * np.max(r.du)
+    assert np.max(np.abs(g["hist"][:, 1] - r.dy)) < 1e-4 * max(np.max(r.dy), 1e-30)
+    assert np.max(np.abs(g["hist"][:, 3] - r.surrogate) / np.abs(r.surrogate)) < 1e-5
+    e_ref = O.energy(r.u, s, B, lam_f)
+    assert abs(g["stats"]["energy"] - e_ref) < 1e-4 * abs(e_ref)
+    if q == 1:
+        assert np.all(g["u"] == 1.0) and np.all(g["labels"] == 0)
+
+
+@pytest.mark.parametrize("store,atol_u,e_rel", [("f32", 2e-5, 1e-5), ("f16", 5e-3, 1e-3)])
+def test_primal_dual_c2_full_size_prefix(store, atol_u, e_rel):
+    # 1024^2 RGB, q=5, J=4 in the benchmark's launch configuration; 2 oracle iterations
+    w = make_c2()
+    K, tau, sigma = 2, 2.0, 0.5
+    key = "_pd_c2_oracle"
+    cache = test_primal_dual_c2_full_size_prefix.__dict__
+    if key not in cache:
+        s = O.datacost(f32(w.img), f32(w.codebook))
+        B = O.filter_bank(w.n, w.J)
+        lam_f = O.lambda_per_filter(w.lam, w.J)
+        cache[key] = (O.primal_dual(s, B, lam_f, tau, sigma, K), s, B, lam_f)
+    r, s, B, lam_f = cache[key]
+    g = run_gpu_pd(w, K, tau, sigma, store=store)
+    assert np.max(np.abs(g["u"] - r.u)) < atol_u
+    e_ref = O.energy(r.u, s, B, lam_f)
+    assert abs(g["stats"]["energy"] - e_ref) < e_rel * abs(e_ref)
+    assert np.mean(g["labels"] == r.labels) >= 0.999
+
+
+def test_primal_dual_and_admm_reach_the_same_minimum():
+    # both solvers minimise the same convex functional: their energies meet (GPU only)
+    w = make_small(64, 3, 2, seed=8, lam=0.1, iters=1)
+    pd = run_gpu_pd(w, 3000, 0.9, 0.9)
+    ad = run_gpu(w, iters=3000, hist=False)
+    e_pd, e_ad = pd["stats"]["energy"], ad["stats"]["energy"]
+    assert abs(e_pd - e_ad) < 1e-4 * abs(e_ad)
+    assert np.mean(pd["labels"] == ad["labels"]) > 0.99
+
+
+def test_primal_dual_lambda_zero_and_errors():
+    pkg = _pkg()
+    w = make_small(128, 4, 2, seed=3, lam=0.0, iters=1)
+    g = run_gpu_pd(w, 2, 1e4, 1e-4)
+    s = g["s"].cpu().numpy()
+    assert np.array_equal(g["labels"], np.argmin(s, axis=0))
+    plan, ws, sd = g["plan"], g["ws"], g["s"]
+    for tau, sigma, lam in ((1.0, 1.5, w.lam), (0.0, 1.0, w.lam), (1.0, float("nan"), w.lam),
+                            (1.0, 1.0, [0.1, 0.2]), (1.0, 1.0, [0.0, -0.1, 0.1])):
+        with pytest.raises(pkg.ShsError) as e:
+            plan.solve_pd(sd, ws, lam, tau, sigma, 2)
+        assert e.value.status == pkg.SHS_E_INVALID
+
+
 def test_lambda_zero_argmin_exact():
     w = make_small(128, 4, 2, seed=3, lam=0.0, iters=1)
     g = run_gpu(w, iters=1)
