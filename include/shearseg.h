@@ -191,6 +191,22 @@ shs_status shs_solve_pd(const shs_plan* plan, const shs_pd_params* params, const
                         size_t ws_bytes, float* d_u, int32_t* d_labels, double* d_hist, shs_stats* h_stats,
                         void* stream);
 
+/* TV comparison model of Section 4 (the labels' gradients coupled per pixel):
+ *   min_u <u, s> + lambda sum_pixels (sum_l |grad u_l|^2)^(1/2) + iota_C(u),
+ * with the periodic forward-difference gradient, solved by the ADMM of Section 3 with grad
+ * in place of S (the paper names no solver for it):
+ *   u = (I + grad^T grad)^{-1} [grad^T (v - b_v) + (w - b_w) - gamma s]   (on the DFT)
+ *   v = shrink_{gamma lambda}(b_v + grad u) per pixel over the 2q-vector,  w = P_C(b_w + u),
+ *   b_v += grad u - v,  b_w += u - w,   from the zero state.
+ * params: lambda_len must be 1 (one weight), gamma > 0, iters, tol/check_every as for
+ * shs_solve; resume must be 0.  q <= 8.  The state (2q images in the plan's storage type)
+ * uses the workspace of the shearlet solver.  Outputs, d_hist rows and h_stats as
+ * shs_solve (energy = <w^K, s> + lambda TV(w^K); the surrogate uses lambda sum |v|).
+ * Errors: SHS_E_INVALID, SHS_E_UNSUPPORTED, SHS_E_WORKSPACE, SHS_E_DEVICE, SHS_E_NUMERIC. */
+shs_status shs_solve_tv(const shs_plan* plan, const shs_params* params, const float* d_s, void* d_ws,
+                        size_t ws_bytes, float* d_u, int32_t* d_labels, double* d_hist, shs_stats* h_stats,
+                        void* stream);
+
 /* Energy F(u) = <u, s> + sum_l sum_j lambda_j ||S_j u_l||_1 of (problemSegmentation) for a
  * given u (float32 [q][N][N]; the indicator term is not evaluated).  Uses params->lambda /
  * lambda_len only.  Synchronises the stream; result in *h_energy (FP64 accumulation). */

@@ -74,6 +74,8 @@ _SIGS = {
                          ctypes.POINTER(ShsStats), _VP]),
     "shs_solve_pd": (_I32, [_VP, ctypes.POINTER(ShsPdParams), _VP, _VP, _SZ, _VP, _VP, _VP,
                             ctypes.POINTER(ShsStats), _VP]),
+    "shs_solve_tv": (_I32, [_VP, ctypes.POINTER(ShsParams), _VP, _VP, _SZ, _VP, _VP, _VP,
+                            ctypes.POINTER(ShsStats), _VP]),
     "shs_energy": (_I32, [_VP, ctypes.POINTER(ShsParams), _VP, _VP, _VP, _SZ,
                           ctypes.POINTER(ctypes.c_double), _VP]),
     "shs_batch_create": (_I32, [_I32, ctypes.POINTER(ShsShape), ctypes.c_int, ctypes.POINTER(_VP)]),
@@ -276,6 +278,24 @@ class Plan:
                                   _ptr(labels), _ptr(hist), ctypes.byref(st) if want_stats else None,
                                   _stream(stream)), "shs_solve_pd")
         del arr
+        return st.as_dict() if want_stats else None
+
+    def solve_tv(self, s, ws, lam, gamma, iters, u=None, labels=None, hist=None, want_stats=True, tol=0.0,
+                 check_every=1, stream=None):
+        """TV comparison model (shs_solve_tv): `lam` is the single TV weight."""
+        _expect(s, (self.q, self.n, self.n), "f32", "d_s")
+        if u is not None:
+            _expect(u, (self.q, self.n, self.n), "f32", "d_u")
+        if labels is not None:
+            _expect(labels, (self.n, self.n), "i32", "d_labels")
+        if hist is not None:
+            _expect(hist, (iters, 4), "f64", "d_hist")
+        prm, keep = _params([lam], gamma, iters, tol, check_every, False)
+        st = ShsStats()
+        _check(lib().shs_solve_tv(self.handle, ctypes.byref(prm), _ptr(s), _ptr(ws), ws.numel(), _ptr(u),
+                                  _ptr(labels), _ptr(hist), ctypes.byref(st) if want_stats else None,
+                                  _stream(stream)), "shs_solve_tv")
+        del keep
         return st.as_dict() if want_stats else None
 
     def energy(self, s, u, ws, lam, stream=None) -> float:

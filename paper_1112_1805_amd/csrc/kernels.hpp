@@ -51,6 +51,8 @@ template <> struct Store<ST_F32> {
     *reinterpret_cast<float2*>(p) = make_float2(a, b);
   }
   __device__ __forceinline__ static float round(float a) { return a; }
+  __device__ __forceinline__ static float to_float(T a) { return a; }
+  __device__ __forceinline__ static T from_float(float a) { return a; }
 };
 template <> struct Store<ST_BF16> {
   using T = uint16_t;
@@ -63,6 +65,8 @@ template <> struct Store<ST_BF16> {
     *reinterpret_cast<uint32_t*>(p) = f2_to_bf16x2(a, b);
   }
   __device__ __forceinline__ static float round(float a) { return bf16_to_f(f_to_bf16(a)); }
+  __device__ __forceinline__ static float to_float(T a) { return bf16_to_f(a); }
+  __device__ __forceinline__ static T from_float(float a) { return f_to_bf16(a); }
 };
 template <> struct Store<ST_F16> {
   using T = uint16_t;
@@ -75,6 +79,8 @@ template <> struct Store<ST_F16> {
     *reinterpret_cast<uint32_t*>(p) = uint32_t(f_to_f16(a)) | (uint32_t(f_to_f16(b)) << 16);
   }
   __device__ __forceinline__ static float round(float a) { return f16_to_f(f_to_f16(a)); }
+  __device__ __forceinline__ static float to_float(T a) { return f16_to_f(a); }
+  __device__ __forceinline__ static T from_float(float a) { return f_to_f16(a); }
 };
 
 // ---------------------------------------------------------------- FP64 block reduction

@@ -15,6 +15,7 @@
 #include "shearseg.h"
 #include "kernels.hpp"
 #include "generic.hpp"
+#include "tv.hpp"
 
 using namespace shs;
 
@@ -26,6 +27,7 @@ struct shs_plan {
   FftPlan prow, pcol;  // mixed-radix stage lists (generic path)
   float* psi;          // [eta][N][PP] dense filter bank (half spectrum)
   float2* tw;          // [N] exp(-2 pi i m / N)
+  float* eig;          // [N] 4 sin^2(pi k / N): DFT eigenvalues of one forward-difference pair (TV)
   // pruned layout
   float* psiw;         // filter values inside each column window
   int4* pwin;          // [eta][M+1] {a, L, value offset, 0}
@@ -80,11 +82,13 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // ---------------------------------------------------------------- kernel timing
 enum KClass {
   KC_ROW_SOLVE, KC_COL_SYN, KC_COL_ANA, KC_COL_FINAL, KC_COL_FWD, KC_ROW_C2R, KC_ROW_R2C, KC_ROW_PRIME,
-  KC_ROW_ENERGY, KC_PIXEL, KC_REDUCE, KC_OTHER, KC_BATCH, KC_ROW_SHRINK, KC_ROW_PD, KC_COUNT
+  KC_ROW_ENERGY, KC_PIXEL, KC_REDUCE, KC_OTHER, KC_BATCH, KC_ROW_SHRINK, KC_ROW_PD, KC_TV_RHS, KC_TV_UPDATE,
+  KC_COL_SOLVE, KC_COUNT
 };
 const char* const kKClassName[KC_COUNT] = {"row_solve", "col_syn", "col_ana", "col_final", "col_fwd", "row_c2r",
                                            "row_r2c", "row_prime", "row_energy", "pixel", "reduce", "other",
-                                           "batch_solve", "row_shrink", "row_pd"};
+                                           "batch_solve", "row_shrink", "row_pd", "tv_rhs", "tv_update",
+                                           "col_solve"};
 
 struct Prof {
   std::mutex mu;
@@ -410,6 +414,31 @@ void run_col(const Ctx& c, int kind, const ColParams& cp, int nblocks, int label
   c.ops.col(c.p, kind, cp, nblocks, labels, c.s);
 }
 
+template <int N>
+void launch_col_solve(const ColParams& cp, const float* eig, int nblocks, int labels, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_solve<N>, dim3(nblocks, labels), dim3(ColCfg<N>::THREADS), 0, s, cp, eig);
+}
+
+// u-step of the TV model on per-label spectra: Z = V / (1 + eigenvalues) column-wise.
+void run_col_solve(const Ctx& c, const ColParams& cp, int labels) {
+  const shs_plan* p = c.p;
+  Timed tm(c.s, KC_COL_SOLVE);
+  if (p->generic) {
+    const size_t e = size_t(p->n) * kGW * sizeof(float2);
+    hipLaunchKernelGGL(k_colg_solve, dim3(p->NS, labels), dim3(256), 2 * e, c.s, cp,
+                       GenParams{p->prow, p->pcol, p->n}, p->eig);
+    return;
+  }
+  switch (p->n) {
+    case 64: launch_col_solve<64>(cp, p->eig, p->NS, labels, c.s); break;
+    case 128: launch_col_solve<128>(cp, p->eig, p->NS, labels, c.s); break;
+    case 256: launch_col_solve<256>(cp, p->eig, p->NS, labels, c.s); break;
+    case 512: launch_col_solve<512>(cp, p->eig, p->NS, labels, c.s); break;
+    case 1024: launch_col_solve<1024>(cp, p->eig, p->NS, labels, c.s); break;
+    case 2048: launch_col_solve<2048>(cp, p->eig, p->NS, labels, c.s); break;
+  }
+}
+
 // S: real images [count][N][N] -> pruned coefficient spectra T1 (count * eta planes).
 void enqueue_synthesis(const Ctx& c, const float* real_in, int count) {
   const shs_plan* p = c.p;
@@ -501,7 +530,8 @@ shs_status energy_of(const Ctx& c, const float* d_u, const float* d_s, double* o
 // ---------------------------------------------------------------- plan construction
 void free_plan(shs_plan* p) {
   if (!p) return;
-  void* bufs[] = {p->psi, p->tw, p->psiw, p->pwin, p->tcol, p->items_syn, p->items_ana, p->flist, p->strips_ana};
+  void* bufs[] = {p->psi, p->tw, p->eig, p->psiw, p->pwin, p->tcol, p->items_syn, p->items_ana, p->flist,
+                  p->strips_ana};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -676,6 +706,92 @@ void enqueue_iteration(const Ctx& c, const float* d_s, float gamma, bool have_ad
   rp.emit = emit ? 1 : 0;
   run_row(c, ROW_SOLVE, p->store, stats, rp, q * p->eta);
   if (stats) enqueue_reduce(c, L.nrow_parts + npix_blocks, hist_row, gamma);
+}
+
+template <int ST>
+void launch_tv_update(bool stats, dim3 grid, hipStream_t s, const TvParams& tp) {
+  if (stats) hipLaunchKernelGGL((k_tv_update<ST, true>), grid, dim3(256), 0, s, tp);
+  else hipLaunchKernelGGL((k_tv_update<ST, false>), grid, dim3(256), 0, s, tp);
+}
+
+TvParams tv_params(const Ctx& c, const float* d_s, float lambda, float gamma) {
+  const shs_plan* p = c.p;
+  TvParams tp{};
+  tp.g = c.ws + c.L.g;
+  tp.g_out = c.ws + c.L.g;
+  tp.w = c.at<float>(c.L.w);
+  tp.bw = c.at<float>(c.L.bw);
+  tp.s = d_s;
+  tp.u = c.at<float>(c.L.zs);
+  tp.rhs = c.at<float>(c.L.us);
+  tp.partials = c.at<double>(c.L.parts);
+  tp.n = p->n;
+  tp.q = p->q;
+  tp.gamma = gamma;
+  tp.lambda = lambda;
+  tp.radius = gamma * lambda;
+  return tp;
+}
+
+// One ADMM iteration of the TV model: right-hand side (grad^T of v - b_v, w - b_w, data
+// term), the u-solve on the DFT (row R2C, column FFT / divide / inverse, row C2R), then
+// the pixel update of g, w, b_w with residual partials.
+void enqueue_tv_iteration(const Ctx& c, const float* d_s, float lambda, float gamma, bool stats, double* hist_row) {
+  const shs_plan* p = c.p;
+  const Layout& L = c.L;
+  const int q = p->q;
+  const long long n2 = (long long)p->n * p->n;
+  const dim3 gpix{unsigned((n2 + 255) / 256)}, bpix{256};
+  const TvParams tp = tv_params(c, d_s, lambda, gamma);
+  {
+    Timed tm(c.s, KC_TV_RHS);
+    switch (p->store) {
+      case ST_F32: hipLaunchKernelGGL((k_tv_rhs<ST_F32>), gpix, bpix, 0, c.s, tp); break;
+      case ST_BF16: hipLaunchKernelGGL((k_tv_rhs<ST_BF16>), gpix, bpix, 0, c.s, tp); break;
+      default: hipLaunchKernelGGL((k_tv_rhs<ST_F16>), gpix, bpix, 0, c.s, tp); break;
+    }
+  }
+  RowParams rp{};
+  rp.real_in = c.at<float>(L.us);
+  rp.spec_out = c.at<float2>(L.v);
+  rp.lout = dense_layout(p);
+  run_row(c, ROW_R2C, ST_F32, false, rp, q);
+  ColParams cp = col_params(c, q);
+  cp.in = c.at<float2>(L.v);
+  cp.out = c.at<float2>(L.z);
+  run_col_solve(c, cp, q);
+  RowParams rz{};
+  rz.spec_in = c.at<float2>(L.z);
+  rz.lin = dense_layout(p);
+  rz.real_out = c.at<float>(L.zs);
+  run_row(c, ROW_C2R, ST_F32, false, rz, q);
+  {
+    Timed tm(c.s, KC_TV_UPDATE);
+    switch (p->store) {
+      case ST_F32: launch_tv_update<ST_F32>(stats, gpix, c.s, tp); break;
+      case ST_BF16: launch_tv_update<ST_BF16>(stats, gpix, c.s, tp); break;
+      default: launch_tv_update<ST_F16>(stats, gpix, c.s, tp); break;
+    }
+  }
+  if (stats) enqueue_reduce(c, (n2 + 255) / 256, hist_row, gamma);
+}
+
+// <w, s> + lambda TV(w) (FP64), synchronising.
+shs_status tv_energy_of(const Ctx& c, const float* d_s, float lambda, double* out) {
+  const long long n2 = (long long)c.p->n * c.p->n;
+  TvParams tp = tv_params(c, d_s, lambda, 1.f);
+  {
+    Timed tm(c.s, KC_OTHER);
+    hipLaunchKernelGGL(k_tv_energy, dim3(unsigned((n2 + 255) / 256)), dim3(256), 0, c.s, tp);
+  }
+  enqueue_reduce(c, (n2 + 255) / 256, nullptr, 1.0);
+  LAUNCHCHK("tv energy");
+  double tot[8];
+  HIPCHK(hipMemcpyAsync(tot, c.at<double>(c.L.sdev), 5 * 8, hipMemcpyDeviceToHost, c.s));
+  HIPCHK(hipStreamSynchronize(c.s));
+  if (tot[4] != 0.0) return fail(SHS_E_NUMERIC, "non-finite energy");
+  *out = tot[SLOT_WS] + tot[SLOT_L1];
+  return SHS_OK;
 }
 
 // One primal-dual iteration (Chambolle-Pock for the functional of Section 3):
@@ -881,7 +997,14 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
     const double a = -2.0 * M_PI * double(m) / double(n);
     tw[m] = make_float2(float(std::cos(a)), float(std::sin(a)));
   }
-  if (hipMemcpy(p->tw, tw.data(), size_t(n) * 8, hipMemcpyHostToDevice) != hipSuccess ||
+  std::vector<float> eig(n);
+  for (int k = 0; k < n; ++k) {
+    const double sn = std::sin(M_PI * double(k) / double(n));
+    eig[k] = float(4.0 * sn * sn);
+  }
+  if (hipMalloc(&p->eig, size_t(n) * 4) != hipSuccess) { free_plan(p); return fail(SHS_E_NOMEM, "eigenvalue table"); }
+  if (hipMemcpy(p->eig, eig.data(), size_t(n) * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->tw, tw.data(), size_t(n) * 8, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(p->psi, 0, psi_bytes) != hipSuccess) {
     free_plan(p);
     return fail(SHS_E_DEVICE, "plan initialisation copy");
@@ -896,10 +1019,17 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
   if (p->generic) {
     // generic column passes hold 3 strips of N x 4 bins in dynamic LDS (up to 96 KB)
     const int lds3 = 3 * n * kGW * int(sizeof(float2));
+    const int lds2 = 2 * n * kGW * int(sizeof(float2));
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colg_syn), hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds3) != hipSuccess ||
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colg_ana), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            lds3) != hipSuccess) {
+                            lds3) != hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colg_fwd), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds2) != hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colg_final), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds2) != hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colg_solve), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds2) != hipSuccess) {
       free_plan(p);
       return fail(SHS_E_DEVICE, "cannot reserve LDS for the mixed-radix column passes");
     }
@@ -1001,6 +1131,61 @@ shs_status shs_solve_pd(const shs_plan* p, const shs_pd_params* prm, const float
     double e = 0.0;
     st = energy_of(c, c.at<float>(c.L.w), d_s, &e);
     if (st != SHS_OK) return st;
+    out.energy = e;
+    *h_stats = out;
+  }
+  return SHS_OK;
+}
+
+shs_status shs_solve_tv(const shs_plan* p, const shs_params* prm, const float* d_s, void* d_ws, size_t ws_bytes,
+                        float* d_u, int32_t* d_labels, double* d_hist, shs_stats* h_stats, void* stream) {
+  if (!p || !prm || !d_s || !prm->lambda) return fail(SHS_E_INVALID, "null argument");
+  shs_status st = check_params(prm);
+  if (st != SHS_OK) return st;
+  if (prm->lambda_len != 1) return fail(SHS_E_INVALID, "the TV model takes one weight (lambda_len = 1)");
+  const float lam = prm->lambda[0];
+  if (!(lam >= 0.f) || !std::isfinite(lam)) return fail(SHS_E_INVALID, "lambda must be finite and >= 0");
+  if (prm->resume) return fail(SHS_E_INVALID, "the TV solver starts from the zero state only");
+  if (p->q > kTvMaxLabels) return fail(SHS_E_UNSUPPORTED, "too many labels for the TV solver");
+  DeviceGuard dg(p->device);
+  Ctx c;
+  st = make_ctx(p, d_ws, ws_bytes, stream, c);
+  if (st != SHS_OK) return st;
+  const long long n2 = (long long)p->n * p->n;
+  enqueue_zero_state(c);
+  LAUNCHCHK("initial state");
+  const double rnorm = std::sqrt(double(p->q) * double(n2));
+  double tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  bool have = false;
+  int done = 0;
+  for (int it = 0; it < prm->iters; ++it) {
+    const bool last = it == prm->iters - 1;
+    const bool check = prm->tol > 0.0 && ((it + 1) % prm->check_every == 0 || last);
+    const bool stats = d_hist != nullptr || check || (last && h_stats != nullptr);
+    enqueue_tv_iteration(c, d_s, lam, prm->gamma, stats, d_hist ? d_hist + 4LL * it : nullptr);
+    LAUNCHCHK("TV iteration");
+    done = it + 1;
+    if (check || (last && h_stats)) {
+      HIPCHK(hipMemcpyAsync(tot, c.at<double>(c.L.sdev), 5 * 8, hipMemcpyDeviceToHost, c.s));
+      HIPCHK(hipStreamSynchronize(c.s));
+      have = true;
+      if (tot[4] != 0.0) return fail(SHS_E_NUMERIC, "non-finite residual at iteration " + std::to_string(it + 1));
+      if (check && std::sqrt(tot[SLOT_DY2] + tot[SLOT_DB2]) <= prm->tol * rnorm) break;
+    }
+  }
+  enqueue_epilogue(c, d_u, d_labels);
+  LAUNCHCHK("epilogue");
+  if (h_stats) {
+    shs_stats out{};
+    out.iters_done = done;
+    if (have) {
+      out.r_primal = std::sqrt(tot[SLOT_DB2]);
+      out.r_dual = std::sqrt(tot[SLOT_DY2]) / prm->gamma;
+      out.r_combined = tot[SLOT_DY2] + tot[SLOT_DB2];
+      out.energy_surrogate = tot[SLOT_WS] + tot[SLOT_L1];
+    }
+    double e = 0.0;
+    if ((st = tv_energy_of(c, d_s, lam, &e)) != SHS_OK) return st;
     out.energy = e;
     *h_stats = out;
   }

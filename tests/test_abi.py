@@ -24,7 +24,7 @@ def test_header_declares_expected_entry_points():
     syms = declared_symbols()
     for name in ["shs_plan_create", "shs_plan_destroy", "shs_workspace_bytes", "shs_state_bytes",
                  "shs_num_filters", "shs_filters", "shs_datacost", "shs_shearlet_forward",
-                 "shs_shearlet_adjoint", "shs_shearlet_denoise", "shs_solve", "shs_solve_pd", "shs_energy", "shs_status_str", "shs_last_error",
+                 "shs_shearlet_adjoint", "shs_shearlet_denoise", "shs_solve", "shs_solve_pd", "shs_solve_tv", "shs_energy", "shs_status_str", "shs_last_error",
                  "shs_batch_create", "shs_batch_destroy", "shs_batch_workspace_bytes", "shs_solve_batch",
                  "shs_profile_begin", "shs_profile_end"]:
         assert name in syms
@@ -80,3 +80,4 @@ def test_null_arguments():
     assert L.shs_shearlet_forward(None, 1, None, None, None, 0, None) == pkg.SHS_E_INVALID
     assert L.shs_shearlet_denoise(None, 1, None, 0, None, None, None, 0, None) == pkg.SHS_E_INVALID
     assert L.shs_solve_pd(None, None, None, None, 0, None, None, None, None, None) == pkg.SHS_E_INVALID
+    assert L.shs_solve_tv(None, None, None, None, 0, None, None, None, None, None) == pkg.SHS_E_INVALID

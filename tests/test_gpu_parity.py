@@ -424,6 +424,79 @@ def test_primal_dual_lambda_zero_and_errors():
         assert e.value.status == pkg.SHS_E_INVALID
 
 
+# ------------------------------------------------------------------ TV comparison model
+def run_gpu_tv(w, iters, lam, gamma=1.0, store="f32"):
+    pkg = _pkg()
+    n, q = w.n, w.q
+    plan = pkg.Plan(n, w.channels, q, w.J, store)
+    ws = plan.new_workspace()
+    s = torch.empty((q, n, n), dtype=torch.float32, device="cuda:0")
+    plan.datacost(dev_t(w.img), w.codebook, s)
+    u = torch.empty((q, n, n), dtype=torch.float32, device="cuda:0")
+    labels = torch.empty((n, n), dtype=torch.int32, device="cuda:0")
+    h = torch.zeros((max(iters, 1), 4), dtype=torch.float64, device="cuda:0")
+    st = plan.solve_tv(s, ws, lam, gamma, iters, u=u, labels=labels, hist=h[:iters] if iters else None)
+    torch.cuda.synchronize()
+    return dict(u=u.cpu().numpy(), labels=labels.cpu().numpy(), stats=st, hist=h.cpu().numpy()[:iters], s=s,
+                plan=plan, ws=ws)
+
+
+TV_CASES = [(64, 3, 1, 20, 0.2, 1.0), (128, 5, 3, 15, 0.1, 0.5), (96, 4, 1, 15, 0.2, 1.0),
+            (160, 2, 1, 10, 0.3, 2.0), (256, 8, 1, 8, 0.05, 1.0), (64, 1, 1, 5, 0.2, 1.0)]
+
+
+@pytest.mark.parametrize("n,q,C,iters,lam,gamma", TV_CASES)
+def test_tv_matches_oracle(n, q, C, iters, lam, gamma):
+    w = make_small(n, q, 1, channels=C, seed=5 * n + q, iters=iters)
+    s = O.datacost(f32(w.img), f32(w.codebook))
+    r = O.tv_admm(s, lam, gamma, iters)
+    g = run_gpu_tv(w, iters, lam, gamma)
+    assert np.max(np.abs(g["u"] - r.w)) < 5e-5
+    assert np.mean(g["labels"] == r.labels) >= 0.999
+    assert np.max(np.abs(g["hist"][:, 0] - r.r_primal)) < 1e-4 * np.max(r.r_primal)
+    assert np.max(np.abs(g["hist"][:, 1] - r.r_dual)) < 1e-4 * np.max(r.r_dual)
+    assert np.max(np.abs(g["hist"][:, 3] - r.surrogate) / np.abs(r.surrogate)) < 1e-5
+    e_ref = O.tv_energy(r.w, s, lam)
+    assert abs(g["stats"]["energy"] - e_ref) < 1e-5 * abs(e_ref)
+    if q == 1:
+        assert np.all(g["u"] == 1.0)
+
+
+@pytest.mark.parametrize("store,atol_u,e_rel", [("f32", 2e-5, 1e-5), ("f16", 5e-3, 1e-3), ("bf16", 3e-2, 1e-2)])
+def test_tv_c2_full_size_prefix(store, atol_u, e_rel):
+    w = make_c2()
+    K, lam, gamma = 3, 0.05, 1.0
+    key = "_tv_c2_oracle"
+    cache = test_tv_c2_full_size_prefix.__dict__
+    if key not in cache:
+        s = O.datacost(f32(w.img), f32(w.codebook))
+        cache[key] = (O.tv_admm(s, lam, gamma, K), s)
+    r, s = cache[key]
+    g = run_gpu_tv(w, K, lam, gamma, store=store)
+    assert np.max(np.abs(g["u"] - r.w)) < atol_u
+    e_ref = O.tv_energy(r.w, s, lam)
+    assert abs(g["stats"]["energy"] - e_ref) < e_rel * abs(e_ref)
+    assert np.mean(g["labels"] == r.labels) >= 0.999
+
+
+def test_tv_errors_and_zero_iterations():
+    pkg = _pkg()
+    w = make_small(64, 3, 1, seed=2, iters=1)
+    g = run_gpu_tv(w, 0, 0.1)
+    assert np.all(g["u"] == 0.0)
+    plan, ws, s = g["plan"], g["ws"], g["s"]
+    for lam, gamma in (([0.1, 0.2], 1.0), ([-0.1], 1.0), ([float("inf")], 1.0), ([0.1], 0.0)):
+        prm_lam = lam if len(lam) != 1 else lam[0]
+        with pytest.raises(pkg.ShsError) as e:
+            if len(lam) == 1:
+                plan.solve_tv(s, ws, prm_lam, gamma, 2)
+            else:
+                prm, keep = pkg._params(lam, gamma, 2)
+                pkg._check(pkg.lib().shs_solve_tv(plan.handle, pkg.ctypes.byref(prm), pkg._ptr(s), pkg._ptr(ws),
+                                                  ws.numel(), None, None, None, None, pkg._stream(None)), "tv")
+        assert e.value.status == pkg.SHS_E_INVALID
+
+
 def test_lambda_zero_argmin_exact():
     w = make_small(128, 4, 2, seed=3, lam=0.0, iters=1)
     g = run_gpu(w, iters=1)
