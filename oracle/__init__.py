@@ -6,7 +6,7 @@ Shearlet Regularization" (arXiv 1112.1805) compute: the Meyer-type building
 blocks and the cone-adapted, translation-invariant finite discrete shearlet
 transform of Section 2, the convex multi-label model and its ADMM of Section 3, and
 the primal-dual iteration the paper names as the alternative at the end of Section 3, and
-the TV comparison model of Section 4.
+the TV and nonlocal comparison models of Section 4.
 Everything is float64 numpy / scipy.fft, with no blocking, fusion
 or reordering beyond what the paper's definitions state.
 
@@ -37,6 +37,7 @@ from .transform import fft2, ifft2, naive_dft2, forward, adjoint, denoise
 from .prox import soft_shrink, project_simplex, project_simplex_paper, project_simplex_bruteforce
 from .model import datacost, lambda_per_filter, admm, energy, labels_of, AdmmResult
 from .primaldual import primal_dual, dual_value, PdResult
+from .nlmodel import nl_graph, window_distances, patch_distance, gaussian_patch, apply_D, apply_Dt, nl_tv, nl_energy, nl_primal_dual, NlResult
 from .tvmodel import grad, grad_adjoint, tv, tv_energy, solve_identity_plus_laplacian, group_shrink, tv_admm, TvResult
 
 __all__ = [
@@ -48,4 +49,6 @@ __all__ = [
     "primal_dual", "dual_value", "PdResult",
     "grad", "grad_adjoint", "tv", "tv_energy", "solve_identity_plus_laplacian", "group_shrink", "tv_admm",
     "TvResult",
+    "nl_graph", "window_distances", "patch_distance", "gaussian_patch", "apply_D", "apply_Dt", "nl_tv",
+    "nl_energy", "nl_primal_dual", "NlResult",
 ]
