@@ -414,6 +414,84 @@ def run_tv(args):
     print(json.dumps(out), flush=True)
 
 
+def run_nl(args):
+    """The nonlocal comparison model of Section 4 (shs_nl_graph + shs_solve_nl) on the C2
+    data: the paper's graph (patch 5, window 15, a = 2, m = 5), one weight, 300
+    primal-dual iterations."""
+    import torch
+    import paper_1112_1805_amd as pkg
+    from synth import make_c2
+    w = make_c2()
+    iters = args.iters if args.iters is not None else w.iters
+    lam = 0.02
+    store = args.store
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    nbr, rev, md = pkg.nl_graph(np.float32(w.img), 5, 15, 2.0, 5)
+    graph_s = time.perf_counter() - t0
+    tau = sigma = float(1.0 / np.sqrt(4.0 * md))
+    plan = pkg.Plan(w.n, w.channels, w.q, 2, store, 0)
+    ws = plan.new_workspace()
+    dn = torch.tensor(nbr, dtype=torch.int32, device=dev)
+    dr = torch.tensor(rev, dtype=torch.int32, device=dev)
+    img = torch.tensor(w.img, dtype=torch.float32, device=dev)
+    s = torch.empty((w.q, w.n, w.n), dtype=torch.float32, device=dev)
+    u = torch.empty_like(s)
+    labels = torch.empty((w.n, w.n), dtype=torch.int32, device=dev)
+    hist = torch.empty((iters, 4), dtype=torch.float64, device=dev)
+
+    def step():
+        plan.datacost(img, w.codebook, s)
+        return plan.solve_nl(s, dn, dr, ws, lam, tau, sigma, iters, md, u=u, labels=labels, hist=hist)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done (nl)")
+    pkg.shs_profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = pkg.shs_profile_end()
+    its = args.steps * iters / dt
+    sb = {"f32": 4, "bf16": 2, "f16": 2}[store]
+    n2, M2 = w.n * w.n, nbr.shape[0]
+    # dual step: y read + written, ubar read (neighbours cached), neighbour ids read
+    amount = (2 * sb * M2 + 4 + 4 * M2 / w.q) * w.q * n2
+    n_launch, tot_ms = prof["nl_dual"]
+    avg_s = tot_ms / n_launch / 1e3
+    out = {
+        "metric": "NL-model primal-dual iters/s at 1024^2 K=5 (comparison model of Section 4)",
+        "value": round(its, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"C2 data (1024x1024 RGB, q=5), NL-means graph (patch 5, window 15, a=2, m=5), "
+                               f"weight {lam}, tau=sigma={tau:.4f}, {iters} iterations, {store} dual variable",
+                   "iters_per_step": iters, "state_storage": store, "max_degree": md},
+        "ms_per_iter": round(dt / args.steps / iters * 1e3, 4),
+        "graph_build_s": round(graph_s, 3),
+        "roofline": {"bound": "hbm", "achieved": round(amount / avg_s / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(amount / avg_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "nl_dual",
+                     "algorithmic_per_launch": amount, "avg_launch_ms": round(avg_s * 1e3, 5)},
+        "kernel_breakdown_ms": {k: {"launches": v[0], "total_ms": round(v[1], 4), "avg_ms": round(v[1] / v[0], 5)}
+                                for k, v in prof.items()},
+        "final_stats": {k: (round(v, 9) if isinstance(v, float) else v) for k, v in st.items()},
+        "source_hash": source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        s64 = oracle.datacost(np.float32(w.img).astype(np.float64), np.float32(w.codebook).astype(np.float64))
+        t0 = time.perf_counter()
+        oracle.nl_primal_dual(s64, nbr.astype(np.int64), lam, tau, sigma, 1)
+        cdt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(1.0 / cdt, 4), "unit": "iters/s", "cores": 1, "kind": "oracle",
+                               "sample": f"1 NL primal-dual iteration of the same workload on the same graph, "
+                                         f"FP64 oracle; {cdt:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def kernel_units(w, iters, eta, store_bytes):
     """Algorithmic bytes / flops per launch of each kernel class (one launch per iteration)."""
     n, q = w.n, w.q
@@ -438,7 +516,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3", "c4", "denoise", "pd", "tv"])
+    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3", "c4", "denoise", "pd", "tv", "nl"])
     ap.add_argument("--store", default=None, choices=["f32", "bf16", "f16"],
                     help="state storage (default f16 for c0-c2/c4, f32 for the c3 batch)")
     ap.add_argument("--iters", type=int, default=None, help="ADMM iterations per step (default: workload's)")
@@ -474,6 +552,9 @@ def main():
         return
     if args.workload == "tv":
         run_tv(args)
+        return
+    if args.workload == "nl":
+        run_nl(args)
         return
     w = workload(args.workload)
     iters = args.iters if args.iters is not None else w.iters

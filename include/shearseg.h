@@ -207,6 +207,50 @@ shs_status shs_solve_tv(const shs_plan* plan, const shs_params* params, const fl
                         size_t ws_bytes, float* d_u, int32_t* d_labels, double* d_hist, shs_stats* h_stats,
                         void* stream);
 
+/* Nonlocal comparison model of Section 4: the NL-means graph replaces the gradient.
+ * Graph parameters (Section 4's values: patch 5, window 15, a = 2, m = 5). */
+typedef struct {
+  int32_t patch;    /* odd patch side p */
+  int32_t window;   /* odd search-window side (<= N) */
+  float a;          /* standard deviation of the patch Gaussian */
+  int32_t m;        /* neighbours picked per pixel, 1..8 (D has 2m blocks) */
+} shs_nl_graph_params;
+
+/* Builds the neighbour graph on the HOST (no device, no plan): for every pixel i in
+ * row-major order, with l its weights already set, the k = min(m, 2m - l) eligible pixels
+ * j of smallest Gaussian-weighted patch distance in the window get w(i, j) = w(j, i) = 1
+ * (eligible: j != i, not yet a neighbour of i, fewer than 2m weights; ties to the smaller
+ * linear index; periodic boundary; colour images sum the distance over channels).
+ * h_img: HOST float32 [channels][N][N].  Outputs (HOST int32 [2m][N][N]): h_nbr[b][i] =
+ * linear index of the b-th neighbour of i (order in which the weights were set) or -1;
+ * h_rev[b][i] = the block b' with h_nbr[b'][h_nbr[b][i]] = i, or -1.  *h_max_degree (may
+ * be NULL) = the largest number of neighbours.  Uses up to 16 host threads. */
+shs_status shs_nl_graph(int32_t n, int32_t channels, const float* h_img, const shs_nl_graph_params* params,
+                        int32_t* h_nbr, int32_t* h_rev, int32_t* h_max_degree);
+
+/* Parameters of the NL solver.  blocks = 2m (rows of the graph arrays), max_degree from
+ * shs_nl_graph; tau, sigma > 0 with tau * sigma * 4 * max_degree <= 1 (||D||^2 <= 4 max degree). */
+typedef struct {
+  float lambda, tau, sigma;
+  int32_t iters;
+  int32_t blocks;
+  int32_t max_degree;
+} shs_nl_params;
+
+/* min <u, s> + lambda sum_i (sum_l sum_b (D_b u_l)(i)^2)^(1/2) + iota_C(u) with the graph
+ * operator D ((D_b u)(i) = u(nbr[b][i]) - u(i), 0 without a b-th neighbour), by the
+ * primal-dual iteration (I + D^T D is not diagonal in the DFT): from u = ubar = y = 0,
+ *   y = P_ball(y + sigma D ubar) per pixel over labels and blocks (radius lambda),
+ *   u' = P_C(u - tau (D^T y + s)),  ubar = 2 u' - u.
+ * d_nbr, d_rev: DEVICE int32 [blocks][N][N] (shs_nl_graph's output).  The dual variable
+ * (q * blocks images, the plan's storage type) lives in the state part of the workspace,
+ * so the plan needs eta >= blocks (J >= 2 for m = 5).  q <= 8.  Outputs, d_hist rows and
+ * h_stats as shs_solve_pd (energy = <u^K, s> + lambda NL-TV(u^K)).
+ * Errors: SHS_E_INVALID, SHS_E_UNSUPPORTED, SHS_E_WORKSPACE, SHS_E_DEVICE, SHS_E_NUMERIC. */
+shs_status shs_solve_nl(const shs_plan* plan, const shs_nl_params* params, const float* d_s, const int32_t* d_nbr,
+                        const int32_t* d_rev, void* d_ws, size_t ws_bytes, float* d_u, int32_t* d_labels,
+                        double* d_hist, shs_stats* h_stats, void* stream);
+
 /* Energy F(u) = <u, s> + sum_l sum_j lambda_j ||S_j u_l||_1 of (problemSegmentation) for a
  * given u (float32 [q][N][N]; the indicator term is not evaluated).  Uses params->lambda /
  * lambda_len only.  Synchronises the stream; result in *h_energy (FP64 accumulation). */

@@ -38,6 +38,16 @@ class ShsPdParams(ctypes.Structure):
                 ("tau", ctypes.c_float), ("sigma", ctypes.c_float), ("iters", ctypes.c_int32)]
 
 
+class ShsNlGraphParams(ctypes.Structure):
+    _fields_ = [("patch", ctypes.c_int32), ("window", ctypes.c_int32), ("a", ctypes.c_float),
+                ("m", ctypes.c_int32)]
+
+
+class ShsNlParams(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_float), ("tau", ctypes.c_float), ("sigma", ctypes.c_float),
+                ("iters", ctypes.c_int32), ("blocks", ctypes.c_int32), ("max_degree", ctypes.c_int32)]
+
+
 class ShsStats(ctypes.Structure):
     _fields_ = [("iters_done", ctypes.c_int32), ("energy", ctypes.c_double),
                 ("energy_surrogate", ctypes.c_double), ("r_primal", ctypes.c_double),
@@ -75,6 +85,10 @@ _SIGS = {
     "shs_solve_pd": (_I32, [_VP, ctypes.POINTER(ShsPdParams), _VP, _VP, _SZ, _VP, _VP, _VP,
                             ctypes.POINTER(ShsStats), _VP]),
     "shs_solve_tv": (_I32, [_VP, ctypes.POINTER(ShsParams), _VP, _VP, _SZ, _VP, _VP, _VP,
+                            ctypes.POINTER(ShsStats), _VP]),
+    "shs_nl_graph": (_I32, [_I32, _I32, _VP, ctypes.POINTER(ShsNlGraphParams), _VP, _VP,
+                            ctypes.POINTER(ctypes.c_int32)]),
+    "shs_solve_nl": (_I32, [_VP, ctypes.POINTER(ShsNlParams), _VP, _VP, _VP, _VP, _SZ, _VP, _VP, _VP,
                             ctypes.POINTER(ShsStats), _VP]),
     "shs_energy": (_I32, [_VP, ctypes.POINTER(ShsParams), _VP, _VP, _VP, _SZ,
                           ctypes.POINTER(ctypes.c_double), _VP]),
@@ -145,6 +159,21 @@ def _params(lam, gamma, iters, tol=0.0, check_every=1, resume=False):
 
 
 # --------------------------------------------------------------------------- C names
+def nl_graph(img, patch: int = 5, window: int = 15, a: float = 2.0, m: int = 5):
+    """shs_nl_graph on a host image [C][N][N]: (nbr, rev) int32 [2m][N][N] and the largest degree."""
+    img = np.ascontiguousarray(np.asarray(img, dtype=np.float32))
+    if img.ndim == 2:
+        img = img[None]
+    C, n, _ = img.shape
+    nbr = np.empty((2 * m, n, n), dtype=np.int32)
+    rev = np.empty((2 * m, n, n), dtype=np.int32)
+    md = ctypes.c_int32(0)
+    prm = ShsNlGraphParams(patch, window, a, m)
+    _check(lib().shs_nl_graph(n, C, img.ctypes.data, ctypes.byref(prm), nbr.ctypes.data, rev.ctypes.data,
+                              ctypes.byref(md)), "shs_nl_graph")
+    return nbr, rev, int(md.value)
+
+
 def shs_num_filters(J: int) -> int:
     return lib().shs_num_filters(J)
 
@@ -296,6 +325,26 @@ class Plan:
                                   _ptr(labels), _ptr(hist), ctypes.byref(st) if want_stats else None,
                                   _stream(stream)), "shs_solve_tv")
         del keep
+        return st.as_dict() if want_stats else None
+
+    def solve_nl(self, s, nbr, rev, ws, lam, tau, sigma, iters, max_degree, u=None, labels=None, hist=None,
+                 want_stats=True, stream=None):
+        """NL model (shs_solve_nl); nbr, rev: device int32 [blocks][N][N] from nl_graph()."""
+        _expect(s, (self.q, self.n, self.n), "f32", "d_s")
+        blocks = nbr.shape[0]
+        _expect(nbr, (blocks, self.n, self.n), "i32", "d_nbr")
+        _expect(rev, (blocks, self.n, self.n), "i32", "d_rev")
+        if u is not None:
+            _expect(u, (self.q, self.n, self.n), "f32", "d_u")
+        if labels is not None:
+            _expect(labels, (self.n, self.n), "i32", "d_labels")
+        if hist is not None:
+            _expect(hist, (iters, 4), "f64", "d_hist")
+        prm = ShsNlParams(float(lam), float(tau), float(sigma), int(iters), int(blocks), int(max_degree))
+        st = ShsStats()
+        _check(lib().shs_solve_nl(self.handle, ctypes.byref(prm), _ptr(s), _ptr(nbr), _ptr(rev), _ptr(ws),
+                                  ws.numel(), _ptr(u), _ptr(labels), _ptr(hist),
+                                  ctypes.byref(st) if want_stats else None, _stream(stream)), "shs_solve_nl")
         return st.as_dict() if want_stats else None
 
     def energy(self, s, u, ws, lam, stream=None) -> float:

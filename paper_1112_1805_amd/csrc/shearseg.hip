@@ -16,6 +16,7 @@
 #include "kernels.hpp"
 #include "generic.hpp"
 #include "tv.hpp"
+#include "nl.hpp"
 
 using namespace shs;
 
@@ -83,12 +84,12 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 enum KClass {
   KC_ROW_SOLVE, KC_COL_SYN, KC_COL_ANA, KC_COL_FINAL, KC_COL_FWD, KC_ROW_C2R, KC_ROW_R2C, KC_ROW_PRIME,
   KC_ROW_ENERGY, KC_PIXEL, KC_REDUCE, KC_OTHER, KC_BATCH, KC_ROW_SHRINK, KC_ROW_PD, KC_TV_RHS, KC_TV_UPDATE,
-  KC_COL_SOLVE, KC_COUNT
+  KC_COL_SOLVE, KC_NL_DUAL, KC_NL_PRIMAL, KC_COUNT
 };
 const char* const kKClassName[KC_COUNT] = {"row_solve", "col_syn", "col_ana", "col_final", "col_fwd", "row_c2r",
                                            "row_r2c", "row_prime", "row_energy", "pixel", "reduce", "other",
                                            "batch_solve", "row_shrink", "row_pd", "tv_rhs", "tv_update",
-                                           "col_solve"};
+                                           "col_solve", "nl_dual", "nl_primal"};
 
 struct Prof {
   std::mutex mu;
@@ -176,7 +177,7 @@ Layout make_layout(const shs_plan* p) {
   L.part = off; off = align256(off + size_t(std::max(p->n_part, 1)) * q * n * p->W * 8);
   L.nrow_parts = (long long)(q * eta) * (n / p->rpb);
   const long long npix = (long long)((nn + 255) / 256);
-  L.nparts = L.nrow_parts + std::max<long long>(npix, kDotBlocks);
+  L.nparts = L.nrow_parts + std::max<long long>(2 * npix, kDotBlocks);
   L.parts = off; off = align256(off + size_t(L.nparts) * 4 * 8);
   L.red1 = off;  off = align256(off + kRed1Blocks * 4 * 8);
   L.sdev = off;  off = align256(off + 8 * 8);
@@ -837,6 +838,19 @@ void enqueue_pd_iteration(const Ctx& c, const float* d_s, float tau, float sigma
   if (stats) enqueue_reduce(c, L.nrow_parts + npix_blocks, hist_row, 1.0);
 }
 
+// KIND 0: dual step, 1: primal step of the NL primal-dual iteration.
+template <int ST, int KIND>
+void launch_nl(bool stats, long long npix, hipStream_t s, const NlParams& p) {
+  const dim3 g{unsigned(npix)}, b{256};
+  if constexpr (KIND == 0) {
+    if (stats) hipLaunchKernelGGL((k_nl_dual<ST, true>), g, b, 0, s, p);
+    else hipLaunchKernelGGL((k_nl_dual<ST, false>), g, b, 0, s, p);
+  } else {
+    if (stats) hipLaunchKernelGGL((k_nl_primal<ST, true>), g, b, 0, s, p);
+    else hipLaunchKernelGGL((k_nl_primal<ST, false>), g, b, 0, s, p);
+  }
+}
+
 }  // namespace
 
 // A batch of images of different sizes and label counts (one plan per distinct shape).
@@ -1187,6 +1201,122 @@ shs_status shs_solve_tv(const shs_plan* p, const shs_params* prm, const float* d
     double e = 0.0;
     if ((st = tv_energy_of(c, d_s, lam, &e)) != SHS_OK) return st;
     out.energy = e;
+    *h_stats = out;
+  }
+  return SHS_OK;
+}
+
+shs_status shs_nl_graph(int32_t n, int32_t channels, const float* h_img, const shs_nl_graph_params* prm,
+                        int32_t* h_nbr, int32_t* h_rev, int32_t* h_max_degree) {
+  if (!h_img || !prm || !h_nbr || !h_rev) return fail(SHS_E_INVALID, "null argument");
+  if (channels < 1 || channels > SHS_MAX_CHANNELS) return fail(SHS_E_INVALID, "channels must be 1..4");
+  if (prm->patch < 1 || prm->patch % 2 == 0) return fail(SHS_E_INVALID, "patch must be odd and >= 1");
+  if (prm->window < 3 || prm->window % 2 == 0) return fail(SHS_E_INVALID, "window must be odd and >= 3");
+  if (n < prm->window || n > 4096) return fail(SHS_E_INVALID, "n must be in window..4096");
+  if (prm->m < 1 || 2 * prm->m > kNlMaxBlocks) return fail(SHS_E_INVALID, "m must be 1..8");
+  if (!(prm->a > 0.f) || !std::isfinite(prm->a)) return fail(SHS_E_INVALID, "a must be finite and > 0");
+  NlGraphCfg g{n, channels, prm->patch, prm->window, prm->m, double(prm->a)};
+  const int md = nl_build_graph(g, h_img, h_nbr, h_rev);
+  if (h_max_degree) *h_max_degree = md;
+  return SHS_OK;
+}
+
+shs_status shs_solve_nl(const shs_plan* p, const shs_nl_params* prm, const float* d_s, const int32_t* d_nbr,
+                        const int32_t* d_rev, void* d_ws, size_t ws_bytes, float* d_u, int32_t* d_labels,
+                        double* d_hist, shs_stats* h_stats, void* stream) {
+  if (!p || !prm || !d_s || !d_nbr || !d_rev) return fail(SHS_E_INVALID, "null argument");
+  if (prm->blocks < 1 || prm->blocks > kNlMaxBlocks) return fail(SHS_E_INVALID, "blocks must be 1..16");
+  if (prm->blocks > p->eta) return fail(SHS_E_UNSUPPORTED, "the plan's state holds q * eta images: need eta >= blocks");
+  if (prm->max_degree < 0 || prm->max_degree > prm->blocks) return fail(SHS_E_INVALID, "bad max_degree");
+  if (!(prm->tau > 0.f) || !(prm->sigma > 0.f) || !std::isfinite(prm->tau) || !std::isfinite(prm->sigma))
+    return fail(SHS_E_INVALID, "tau and sigma must be finite and > 0");
+  if (double(prm->tau) * double(prm->sigma) * 4.0 * std::max(prm->max_degree, 1) > 1.0 + 1e-6)
+    return fail(SHS_E_INVALID, "tau * sigma * 4 * max_degree must be <= 1 (||D||^2 <= 4 max_degree)");
+  if (!(prm->lambda >= 0.f) || !std::isfinite(prm->lambda)) return fail(SHS_E_INVALID, "lambda must be >= 0");
+  if (prm->iters < 0) return fail(SHS_E_INVALID, "iters must be >= 0");
+  DeviceGuard dg(p->device);
+  Ctx c;
+  shs_status st = make_ctx(p, d_ws, ws_bytes, stream, c);
+  if (st != SHS_OK) return st;
+  const long long n2 = (long long)p->n * p->n;
+  const long long npix = (n2 + 255) / 256;
+  enqueue_zero_state(c);
+  {
+    const long long words = (long long)p->q * n2;
+    hipLaunchKernelGGL(k_fill_u32, dim3(unsigned((words + 255) / 256)), dim3(256), 0, c.s,
+                       reinterpret_cast<uint32_t*>(c.at<float>(c.L.us)), words, 0u);
+  }
+  LAUNCHCHK("initial state");
+  NlParams np{};
+  np.y = c.ws + c.L.g;
+  np.u = c.at<float>(c.L.w);
+  np.ubar = c.at<float>(c.L.us);
+  np.s = d_s;
+  np.nbr = d_nbr;
+  np.rev = d_rev;
+  np.n2 = n2;
+  np.q = p->q;
+  np.M2 = prm->blocks;
+  np.lambda = prm->lambda;
+  np.tau = prm->tau;
+  np.sigma = prm->sigma;
+  double tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  bool have = false;
+  for (int it = 0; it < prm->iters; ++it) {
+    const bool last = it == prm->iters - 1;
+    const bool stats = d_hist != nullptr || (last && h_stats != nullptr);
+    NlParams pd = np, pp = np;
+    pd.partials = c.at<double>(c.L.parts);
+    pp.partials = c.at<double>(c.L.parts) + npix * 4;
+    {
+      Timed tm(c.s, KC_NL_DUAL);
+      switch (p->store) {
+        case ST_F32: launch_nl<ST_F32, 0>(stats, npix, c.s, pd); break;
+        case ST_BF16: launch_nl<ST_BF16, 0>(stats, npix, c.s, pd); break;
+        default: launch_nl<ST_F16, 0>(stats, npix, c.s, pd); break;
+      }
+    }
+    {
+      Timed tm(c.s, KC_NL_PRIMAL);
+      switch (p->store) {
+        case ST_F32: launch_nl<ST_F32, 1>(stats, npix, c.s, pp); break;
+        case ST_BF16: launch_nl<ST_BF16, 1>(stats, npix, c.s, pp); break;
+        default: launch_nl<ST_F16, 1>(stats, npix, c.s, pp); break;
+      }
+    }
+    if (stats) enqueue_reduce(c, 2 * npix, d_hist ? d_hist + 4LL * it : nullptr, 1.0);
+    LAUNCHCHK("NL primal-dual iteration");
+    if (last && h_stats) {
+      HIPCHK(hipMemcpyAsync(tot, c.at<double>(c.L.sdev), 5 * 8, hipMemcpyDeviceToHost, c.s));
+      HIPCHK(hipStreamSynchronize(c.s));
+      have = true;
+      if (tot[4] != 0.0) return fail(SHS_E_NUMERIC, "non-finite value in the NL iteration");
+    }
+  }
+  enqueue_epilogue(c, d_u, d_labels);
+  LAUNCHCHK("epilogue");
+  if (h_stats) {
+    shs_stats out{};
+    out.iters_done = prm->iters;
+    if (have) {
+      out.r_primal = std::sqrt(tot[SLOT_DB2]);
+      out.r_dual = std::sqrt(tot[SLOT_DY2]);
+      out.r_combined = tot[SLOT_DY2] + tot[SLOT_DB2];
+      out.energy_surrogate = tot[SLOT_WS] + tot[SLOT_L1];
+    }
+    NlParams pe = np;
+    pe.partials = c.at<double>(c.L.parts);
+    {
+      Timed tm(c.s, KC_OTHER);
+      hipLaunchKernelGGL(k_nl_energy, dim3(unsigned(npix)), dim3(256), 0, c.s, pe);
+    }
+    enqueue_reduce(c, npix, nullptr, 1.0);
+    LAUNCHCHK("NL energy");
+    double e[8];
+    HIPCHK(hipMemcpyAsync(e, c.at<double>(c.L.sdev), 5 * 8, hipMemcpyDeviceToHost, c.s));
+    HIPCHK(hipStreamSynchronize(c.s));
+    if (e[4] != 0.0) return fail(SHS_E_NUMERIC, "non-finite energy");
+    out.energy = e[SLOT_WS] + e[SLOT_L1];
     *h_stats = out;
   }
   return SHS_OK;

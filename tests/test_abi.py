@@ -24,7 +24,7 @@ def test_header_declares_expected_entry_points():
     syms = declared_symbols()
     for name in ["shs_plan_create", "shs_plan_destroy", "shs_workspace_bytes", "shs_state_bytes",
                  "shs_num_filters", "shs_filters", "shs_datacost", "shs_shearlet_forward",
-                 "shs_shearlet_adjoint", "shs_shearlet_denoise", "shs_solve", "shs_solve_pd", "shs_solve_tv", "shs_energy", "shs_status_str", "shs_last_error",
+                 "shs_shearlet_adjoint", "shs_shearlet_denoise", "shs_solve", "shs_solve_pd", "shs_solve_tv", "shs_nl_graph", "shs_solve_nl", "shs_energy", "shs_status_str", "shs_last_error",
                  "shs_batch_create", "shs_batch_destroy", "shs_batch_workspace_bytes", "shs_solve_batch",
                  "shs_profile_begin", "shs_profile_end"]:
         assert name in syms
@@ -81,3 +81,33 @@ def test_null_arguments():
     assert L.shs_shearlet_denoise(None, 1, None, 0, None, None, None, 0, None) == pkg.SHS_E_INVALID
     assert L.shs_solve_pd(None, None, None, None, 0, None, None, None, None, None) == pkg.SHS_E_INVALID
     assert L.shs_solve_tv(None, None, None, None, 0, None, None, None, None, None) == pkg.SHS_E_INVALID
+
+
+@pytest.mark.parametrize("n,C,m,window,seed", [(16, 1, 5, 15, 3), (20, 3, 5, 15, 4), (24, 1, 3, 9, 5), (16, 2, 8, 15, 6)])
+def test_nl_graph_matches_oracle(n, C, m, window, seed):
+    # host-side graph builder of the library (no device) against the oracle's construction
+    import numpy as np
+    import oracle as O
+    from synth import make_small
+    w = make_small(n, 3, 1, channels=C, seed=seed, noise=0.1, iters=1)
+    img = np.float32(w.img)
+    nbr, rev, md = pkg.nl_graph(img, 5, window, 2.0, m)
+    ref = O.nl_graph(img.astype(np.float64), 5, window, 2.0, m)
+    assert np.array_equal(nbr, ref.astype(np.int32))
+    flat = nbr.reshape(2 * m, -1)
+    assert md == int(np.max(np.sum(flat >= 0, axis=0)))
+    for b in range(2 * m):                                     # rev is the position of i in j's list
+        for i in np.nonzero(flat[b] >= 0)[0][:50]:
+            j = flat[b, i]
+            assert flat[rev.reshape(2 * m, -1)[b, i], j] == i
+
+
+def test_nl_graph_validation():
+    import numpy as np
+    img = np.zeros((1, 16, 16), np.float32)
+    for kw in (dict(patch=4), dict(window=14), dict(window=17), dict(m=0), dict(m=9), dict(a=0.0)):
+        args = dict(patch=5, window=15, a=2.0, m=5)
+        args.update(kw)
+        with pytest.raises(pkg.ShsError) as e:
+            pkg.nl_graph(img, **args)
+        assert e.value.status == pkg.SHS_E_INVALID

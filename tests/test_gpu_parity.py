@@ -372,7 +372,7 @@ def test_primal_dual_matches_oracle(n, q, J, C, iters, tau, sigma):
     assert np.mean(g["labels"] == r.labels) >= 0.999
     # per-iteration history: ||du||, ||dy|| (relative to the sequence's size), surrogate
     assert np.max(np.abs(g["hist"][:, 0] - r.du)) < 1e-4 * np.max(r.du)
-    assert np.max(np.abs(g["hist"][:, 1] - r.dy)) < 1e-4 * max(np.max(r.dy), 1e-30)
+    assert np.max(np.abs(g["hist"][:, 1] - r.dy)) < 1e-4 * max(np.max(r.dy), 1e-9)
     assert np.max(np.abs(g["hist"][:, 3] - r.surrogate) / np.abs(r.surrogate)) < 1e-5
     e_ref = O.energy(r.u, s, B, lam_f)
     assert abs(g["stats"]["energy"] - e_ref) < 1e-4 * abs(e_ref)
@@ -495,6 +495,85 @@ def test_tv_errors_and_zero_iterations():
                 pkg._check(pkg.lib().shs_solve_tv(plan.handle, pkg.ctypes.byref(prm), pkg._ptr(s), pkg._ptr(ws),
                                                   ws.numel(), None, None, None, None, pkg._stream(None)), "tv")
         assert e.value.status == pkg.SHS_E_INVALID
+
+
+# ------------------------------------------------------------------ NL (graph) model
+def run_gpu_nl(w, iters, lam, store="f32", J=2, m=5, graph=None, tau=None, sigma=None):
+    pkg = _pkg()
+    n, q = w.n, w.q
+    nbr, rev, md = graph if graph is not None else pkg.nl_graph(np.float32(w.img), 5, 15, 2.0, m)
+    tau = tau if tau is not None else 1.0 / np.sqrt(4.0 * md)
+    sigma = sigma if sigma is not None else 1.0 / np.sqrt(4.0 * md)
+    plan = pkg.Plan(n, w.channels, q, J, store)
+    ws = plan.new_workspace()
+    s = torch.empty((q, n, n), dtype=torch.float32, device="cuda:0")
+    plan.datacost(dev_t(w.img), w.codebook, s)
+    u = torch.empty((q, n, n), dtype=torch.float32, device="cuda:0")
+    labels = torch.empty((n, n), dtype=torch.int32, device="cuda:0")
+    h = torch.zeros((iters, 4), dtype=torch.float64, device="cuda:0")
+    st = plan.solve_nl(s, dev_t(nbr, torch.int32), dev_t(rev, torch.int32), ws, lam, tau, sigma, iters, md,
+                       u=u, labels=labels, hist=h)
+    torch.cuda.synchronize()
+    return dict(u=u.cpu().numpy(), labels=labels.cpu().numpy(), stats=st, hist=h.cpu().numpy(), s=s,
+                plan=plan, ws=ws, nbr=nbr, rev=rev, md=md, tau=tau, sigma=sigma)
+
+
+NL_CASES = [(64, 3, 1, 20, 0.1), (96, 5, 3, 15, 0.05), (72, 2, 1, 10, 0.2), (128, 8, 1, 8, 0.05), (64, 1, 1, 5, 0.1)]
+
+
+@pytest.mark.parametrize("n,q,C,iters,lam", NL_CASES)
+def test_nl_matches_oracle(n, q, C, iters, lam):
+    w = make_small(n, q, 2, channels=C, seed=7 * n + q, iters=iters)
+    g = run_gpu_nl(w, iters, lam)
+    s = O.datacost(f32(w.img), f32(w.codebook))
+    nbr = g["nbr"].astype(np.int64)
+    r = O.nl_primal_dual(s, nbr, lam, g["tau"], g["sigma"], iters)
+    assert np.max(np.abs(g["u"] - r.u)) < 5e-5
+    assert np.mean(g["labels"] == r.labels) >= 0.999
+    assert np.max(np.abs(g["hist"][:, 0] - r.du)) < 1e-4 * np.max(r.du)
+    assert np.max(np.abs(g["hist"][:, 1] - r.dy)) < 1e-4 * max(np.max(r.dy), 1e-9)
+    assert np.max(np.abs(g["hist"][:, 3] - r.surrogate) / np.abs(r.surrogate)) < 1e-5
+    e_ref = O.nl_energy(r.u, s, nbr, lam)
+    assert abs(g["stats"]["energy"] - e_ref) < 1e-5 * abs(e_ref)
+    if q == 1:
+        assert np.all(g["u"] == 1.0)
+
+
+@pytest.mark.parametrize("store,atol_u", [("f32", 2e-5), ("f16", 5e-3)])
+def test_nl_c2_full_size_prefix(store, atol_u):
+    # 1024^2 RGB, q=5: the library's graph (its parity with the oracle's construction is a
+    # CPU test) and 2 oracle primal-dual iterations on it
+    w = make_c2()
+    key = "_nl_c2"
+    cache = test_nl_c2_full_size_prefix.__dict__
+    pkg = _pkg()
+    if key not in cache:
+        graph = pkg.nl_graph(np.float32(w.img), 5, 15, 2.0, 5)
+        s = O.datacost(f32(w.img), f32(w.codebook))
+        t = 1.0 / np.sqrt(4.0 * graph[2])
+        cache[key] = (graph, O.nl_primal_dual(s, graph[0].astype(np.int64), 0.02, t, t, 2), s)
+    graph, r, s = cache[key]
+    g = run_gpu_nl(w, 2, 0.02, store=store, J=4, graph=graph)
+    assert np.max(np.abs(g["u"] - r.u)) < atol_u
+    assert np.mean(g["labels"] == r.labels) >= 0.999
+
+
+def test_nl_errors():
+    pkg = _pkg()
+    w = make_small(64, 3, 2, seed=9, iters=1)
+    g = run_gpu_nl(w, 1, 0.1)
+    plan, ws, s, nbr, rev, md = g["plan"], g["ws"], g["s"], g["nbr"], g["rev"], g["md"]
+    dn, dr = dev_t(nbr, torch.int32), dev_t(rev, torch.int32)
+    with pytest.raises(pkg.ShsError) as e:                 # steps too large for ||D||^2 <= 4 max degree
+        plan.solve_nl(s, dn, dr, ws, 0.1, 1.0, 1.0, 2, md)
+    assert e.value.status == pkg.SHS_E_INVALID
+    with pytest.raises(pkg.ShsError) as e:                 # negative weight
+        plan.solve_nl(s, dn, dr, ws, -0.1, 0.1, 0.1, 2, md)
+    assert e.value.status == pkg.SHS_E_INVALID
+    small = pkg.Plan(64, 1, 3, 1)                          # eta = 5 < 2m = 10 blocks
+    with pytest.raises(pkg.ShsError) as e:
+        small.solve_nl(s, dn, dr, small.new_workspace(), 0.1, 0.1, 0.1, 2, md)
+    assert e.value.status == pkg.SHS_E_UNSUPPORTED
 
 
 def test_lambda_zero_argmin_exact():
