@@ -853,6 +853,8 @@ void launch_nl(bool stats, long long npix, hipStream_t s, const NlParams& p) {
 
 }  // namespace
 
+constexpr int kBatchStreams = 8;   // internal streams of a batch (default priority)
+
 // A batch of images of different sizes and label counts (one plan per distinct shape).
 // Every iteration of all images is one captured graph (images forked over internal
 // streams so that small images run side by side), replayed on the caller's stream.
@@ -860,6 +862,8 @@ struct shs_batch {
   int count = 0, device = 0;
   std::vector<shs_plan*> plans;
   std::vector<int> plan_of;
+  std::vector<int> stream_of;   // stream of each image (longest-first greedy balance)
+  std::vector<int> order;       // images by decreasing estimated cost (capture order)
   std::vector<size_t> ws_off;
   size_t ws_total = 0;
   std::vector<hipStream_t> streams;
@@ -1520,7 +1524,25 @@ shs_status shs_batch_create(int32_t count, const shs_shape* shapes, int device, 
     b->ws_total += align256(shs_workspace_bytes(b->plans[found]));
   }
   DeviceGuard dg(device);
-  const int nstreams = std::min(count, 8);
+  const int nstreams = std::min(count, kBatchStreams);
+  // Balance the streams: an iteration of the batch ends with its slowest stream.  Cost of
+  // an image ~ q eta N^2 log2 N (the mixed-radix path costs about twice as much per
+  // coefficient); largest first onto the least loaded stream.
+  {
+    std::vector<double> cost(count), load(nstreams, 0.0);
+    for (int i = 0; i < count; ++i) {
+      const shs_plan* p = b->plans[b->plan_of[i]];
+      cost[i] = double(p->q) * p->eta * double(p->n) * p->n * std::log2(double(p->n)) * (p->generic ? 2.0 : 1.0);
+      b->order.push_back(i);
+    }
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    b->stream_of.assign(count, 0);
+    for (int i : b->order) {
+      const int k = int(std::min_element(load.begin(), load.end()) - load.begin());
+      b->stream_of[i] = k;
+      load[k] += cost[i];
+    }
+  }
   for (int k = 0; k < nstreams; ++k) {
     hipStream_t s;
     hipEvent_t e;
@@ -1578,7 +1600,7 @@ shs_status shs_solve_batch(shs_batch* b, const shs_params* params, const float* 
     shs_status st = make_ctx(p, static_cast<char*>(d_ws) + b->ws_off[i], shs_workspace_bytes(p), nullptr, ctx[i]);
     if (st == SHS_OK) st = set_lambda(ctx[i], &params[i]);
     if (st != SHS_OK) return fail(st, "image " + std::to_string(i) + ": " + g_err);
-    ctx[i].s = b->streams[i % b->streams.size()];
+    ctx[i].s = b->streams[b->stream_of[i]];
   }
   // graph cache key: every pointer and parameter baked into the graphs
   std::vector<double> key;
@@ -1600,26 +1622,26 @@ shs_status shs_solve_batch(shs_batch* b, const shs_params* params, const float* 
       if (d_stats) hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(64), 0, c.s, c.at<double>(c.L.sdev), 5, d_stats + 5LL * i);
     };
     shs_status st = SHS_OK;
-    if (st == SHS_OK) st = b->capture([&] { for (int i = 0; i < b->count; ++i) enqueue_zero_state(ctx[i]); }, &b->g_init);
+    if (st == SHS_OK) st = b->capture([&] { for (int i : b->order) enqueue_zero_state(ctx[i]); }, &b->g_init);
     if (iters == 0) {
-      if (st == SHS_OK) st = b->capture([&] { for (int i = 0; i < b->count; ++i) tail(i); }, &b->g_last);
+      if (st == SHS_OK) st = b->capture([&] { for (int i : b->order) tail(i); }, &b->g_last);
     } else if (iters == 1) {
       if (st == SHS_OK)
         st = b->capture([&] {
-          for (int i = 0; i < b->count; ++i) { enqueue_iteration(ctx[i], d_s[i], params[i].gamma, false, true, false, nullptr); tail(i); }
+          for (int i : b->order) { enqueue_iteration(ctx[i], d_s[i], params[i].gamma, false, true, false, nullptr); tail(i); }
         }, &b->g_last);
     } else {
       if (st == SHS_OK)
         st = b->capture([&] {
-          for (int i = 0; i < b->count; ++i) enqueue_iteration(ctx[i], d_s[i], params[i].gamma, false, false, true, nullptr);
+          for (int i : b->order) enqueue_iteration(ctx[i], d_s[i], params[i].gamma, false, false, true, nullptr);
         }, &b->g_first);
       if (st == SHS_OK)
         st = b->capture([&] {
-          for (int i = 0; i < b->count; ++i) enqueue_iteration(ctx[i], d_s[i], params[i].gamma, true, false, true, nullptr);
+          for (int i : b->order) enqueue_iteration(ctx[i], d_s[i], params[i].gamma, true, false, true, nullptr);
         }, &b->g_mid);
       if (st == SHS_OK)
         st = b->capture([&] {
-          for (int i = 0; i < b->count; ++i) { enqueue_iteration(ctx[i], d_s[i], params[i].gamma, true, true, false, nullptr); tail(i); }
+          for (int i : b->order) { enqueue_iteration(ctx[i], d_s[i], params[i].gamma, true, true, false, nullptr); tail(i); }
         }, &b->g_last);
     }
     if (st != SHS_OK) { b->drop_graphs(); return st; }
