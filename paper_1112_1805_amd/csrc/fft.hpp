@@ -11,9 +11,10 @@
 //
 // so a thread's input positions equal its output positions: a forward FFT, a
 // pointwise product and an inverse FFT chain in registers without extra exchange.
-// Between stages the points travel through LDS.  Inter-stage twiddles come from a
-// table tw[i] = exp(-2 pi i i / NT) (computed in FP64 on the host, rounded to FP32);
-// twiddles inside a register DFT are compile-time constants.
+// Between stages the points travel through LDS.  Inter-stage twiddles come from a table
+// per FFT configuration, laid out in the order the threads read them (values
+// exp(-2 pi i m / NT) computed in FP64 on the host, rounded to FP32); twiddles inside a
+// register DFT are compile-time constants.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <utility>
@@ -197,13 +198,22 @@ struct ColAddr {
   __device__ __forceinline__ float2* at(int q, int rr) const { return base + (q * RQ + rr) * W; }
 };
 
+// Inter-stage twiddles of one FFT configuration, stored in the order the threads read
+// them so that the lanes of a wave load consecutive entries (a table indexed by the
+// exponent r*t would be read with stride r and touch up to one cache line per lane):
+//   last stage   sw[(r-1) T + t]              = W_L^{r t},       1 <= r < R, t < T
+//   middle stage sw[(R-1) T + (r-1) R + tr]   = W_{R RM}^{r tr}, 1 <= r < RM, tr < R
+// with W_n = exp(-2 pi i / n).  The values are those of the plan's table exp(-2 pi i m / NT)
+// at m = exponent * NT / n, copied on the host.
+template <int L, int R, int RM>
+constexpr int stage_tw_size() { return (R - 1) * (L / R) + (RM - 1) * R; }
+
 // In-register/LDS Stockham FFT of length L.  On entry a[r] holds point t + r*T; on exit
-// a[r] holds output bin t + r*T.  `tw` is the table exp(-2 pi i m / NT), `twstep` = NT / L.
+// a[r] holds output bin t + r*T.  `sw` is the stage twiddle table of (L, R, RM) above.
 // The caller must have synchronised any earlier reader of the LDS region before the call
 // (the routine synchronises before its first LDS write).
 template <int L, int R, int RM, bool INV, int SK, class Addr>
-__device__ __forceinline__ void fft_run(cpx (&a)[R], const Addr& lds, int t,
-                                        const float2* __restrict__ tw, int twstep) {
+__device__ __forceinline__ void fft_run(cpx (&a)[R], const Addr& lds, int t, const float2* __restrict__ sw) {
   static_assert(R * R * RM == L && R % RM == 0, "FFT configuration");
   constexpr int T = L / R;                 // = R * RM
   const int tq = int(unsigned(t) / R);     // t = tq * R + tr
@@ -224,7 +234,7 @@ __device__ __forceinline__ void fft_run(cpx (&a)[R], const Addr& lds, int t,
     fft_sync<SK>();
     cpx w[RM];
     static_for<RM>([&](auto r) {
-      if constexpr (r > 0) w[r] = ld(tw + (r * tr) * (L / (R * RM)) * twstep);
+      if constexpr (r > 0) w[r] = ld(sw + ((R - 1) * T + (r - 1) * R) + tr);
     });
     static_for<U>([&](auto u) {
       cpx c[RM];
@@ -240,11 +250,10 @@ __device__ __forceinline__ void fft_run(cpx (&a)[R], const Addr& lds, int t,
     fft_sync<SK>();
   }
   // last stage: radix R, Ns = L/R, butterfly bf = t; input t + r*T = (tq + r*RM) * R + tr
-  const int twt = t * twstep;
   static_for<R>([&](auto r) {
     cpx v = ld(lds.template at<R>(tq + r * RM, tr));
     if constexpr (r > 0) {
-      cpx w = ld(tw + r * twt);
+      cpx w = ld(sw + (r - 1) * T + t);
       v = INV ? cmulc(v, w) : cmul(v, w);
     }
     a[r] = v;

@@ -66,15 +66,17 @@ __device__ __forceinline__ void dft_any(cpx (&a)[R]) {
 
 // ---------------------------------------------------------------- one Stockham stage
 // `items` = W interleaved transforms x (L / R) butterflies, spread over nthr threads.
-// Element `pos` of transform c lives at buf[pos * W + c].  tw: exp(-2 pi i m / (L*twstep)).
+// Element `pos` of transform c lives at buf[pos * W + c].
+// sw: stage twiddles of the whole transform in thread read order, W_{Ns R}^{i k} at
+// sw[i Ns + k - 1] (1 <= i < R, k < Ns) for the stage of stride Ns and radix R; the stages'
+// ranges [Ns - 1, Ns R - 1) tile [0, L - 1), and consecutive butterflies read consecutive
+// entries.
 template <int R, bool INV, int W>
 __device__ __forceinline__ void gstage(const float2* __restrict__ src, float2* __restrict__ dst, int L, int Ns,
-                                       unsigned mag, int sh, int nthr, int tid, const float2* __restrict__ tw,
-                                       int twstep) {
+                                       unsigned mag, int sh, int nthr, int tid, const float2* __restrict__ sw) {
   static_assert((W & (W - 1)) == 0, "strip width is a power of two");
   const int nb = L / R;
   const int items = nb * W;
-  const int tws = (L / (Ns * R)) * twstep;
   for (int it = tid; it < items; it += nthr) {
     const int c = it & (W - 1);
     const unsigned bf = unsigned(it) / W;
@@ -85,7 +87,7 @@ __device__ __forceinline__ void gstage(const float2* __restrict__ src, float2* _
     if (Ns > 1) {
       static_for<R - 1>([&](auto i1) {
         constexpr int i = i1 + 1;
-        const cpx w = ld(tw + (i * k) * tws);
+        const cpx w = ld(sw + (i * Ns + k - 1));
         a[i] = INV ? cmulc(a[i], w) : cmul(a[i], w);
       });
     }
@@ -97,8 +99,7 @@ __device__ __forceinline__ void gstage(const float2* __restrict__ src, float2* _
 
 // Full transform: data in b0 (natural order) -> result (natural order) in the returned buffer.
 template <bool INV, int SK, int W>
-__device__ float2* gfft(float2* b0, float2* b1, const FftPlan& pl, int nthr, int tid,
-                        const float2* __restrict__ tw, int twstep) {
+__device__ float2* gfft(float2* b0, float2* b1, const FftPlan& pl, int nthr, int tid, const float2* __restrict__ sw) {
   float2* src = b0;
   float2* dst = b1;
   int Ns = 1;
@@ -107,19 +108,19 @@ __device__ float2* gfft(float2* b0, float2* b1, const FftPlan& pl, int nthr, int
     const unsigned mg = pl.mag[s];
     const int sh = pl.sh[s];
     switch (r) {
-      case 2: gstage<2, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
-      case 3: gstage<3, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
-      case 4: gstage<4, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
-      case 5: gstage<5, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
-      case 7: gstage<7, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
-      case 8: gstage<8, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
-      case 9: gstage<9, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
-      case 11: gstage<11, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
-      case 13: gstage<13, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
-      case 16: gstage<16, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
-      case 17: gstage<17, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
-      case 19: gstage<19, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
-      case 23: gstage<23, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, tw, twstep); break;
+      case 2: gstage<2, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 3: gstage<3, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 4: gstage<4, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 5: gstage<5, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 7: gstage<7, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 8: gstage<8, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 9: gstage<9, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 11: gstage<11, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 13: gstage<13, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 16: gstage<16, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 17: gstage<17, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 19: gstage<19, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 23: gstage<23, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
       default: break;
     }
     fft_sync<SK>();
@@ -140,6 +141,10 @@ struct GenParams {
   FftPlan pcol;   // length N
   int n;
 };
+// Twiddle table of a mixed-radix plan, one device array: [0, N) exp(-2 pi i m / N), then
+// the stage table of the row FFT (N/2 entries), then that of the column FFT (N entries).
+__device__ __forceinline__ const float2* row_sw_g(const float2* tw, int n) { return tw + n; }
+__device__ __forceinline__ const float2* col_sw_g(const float2* tw, int n) { return tw + n + n / 2; }
 
 // ---------------------------------------------------------------- generic row pass
 // Same modes and data contract as k_row.  Each wave transforms RW rows at once, stored
@@ -183,7 +188,7 @@ __global__ __launch_bounds__(256) void k_row_g(RowParams p, GenParams gp) {
       }
     }
     fft_sync<SYNC_WAVE>();
-    res = gfft<true, SYNC_WAVE, RW>(b0, b1, gp.prow, 64, lane, p.tw, 2);
+    res = gfft<true, SYNC_WAVE, RW>(b0, b1, gp.prow, 64, lane, row_sw_g(p.tw, n));
   }
   if constexpr (MODE == ROW_C2R) {
     for (int c = 0; c < RW; ++c) {
@@ -208,21 +213,24 @@ __global__ __launch_bounds__(256) void k_row_g(RowParams p, GenParams gp) {
       for (int k = lane; k < M; k += 64) {
         float g0, g1;
         S::unpack(S::load_pair(g + 2 * k), g0, g1);
-        const float b0v = fminf(fmaxf(g0, -th), th), b1v = fminf(fmaxf(g1, -th), th);
+        const float b0v = clip(g0, th), b1v = clip(g1, th);
         float n0 = g0, n1 = g1;
         if constexpr (MODE == ROW_SOLVE) {
           const float2 cc = res[k * RW + c];
-          n0 = S::round(b0v + cc.x);
-          n1 = S::round(b1v + cc.y);
-          S::store2(g + 2 * k, n0, n1);
+          n0 = b0v + cc.x;
+          n1 = b1v + cc.y;
+          S::store_pair(g + 2 * k, S::round2(n0, n1));
         }
-        const float nb0 = fminf(fmaxf(n0, -th), th), nb1 = fminf(fmaxf(n1, -th), th);
+        const float nb0 = clip(n0, th), nb1 = clip(n1, th);
         if constexpr (STATS && MODE == ROW_SOLVE) {
           const float dv0 = (n0 - nb0) - (g0 - b0v), dv1 = (n1 - nb1) - (g1 - b1v);
           const float db0 = nb0 - b0v, db1 = nb1 - b1v;
-          acc[SLOT_DY2] += dv0 * dv0 + dv1 * dv1;
-          acc[SLOT_DB2] += db0 * db0 + db1 * db1;
-          acc[SLOT_L1] += fabsf(n0 - nb0) + fabsf(n1 - nb1);
+          acc[SLOT_DY2] = fmaf(dv0, dv0, acc[SLOT_DY2]);
+          acc[SLOT_DY2] = fmaf(dv1, dv1, acc[SLOT_DY2]);
+          acc[SLOT_DB2] = fmaf(db0, db0, acc[SLOT_DB2]);
+          acc[SLOT_DB2] = fmaf(db1, db1, acc[SLOT_DB2]);
+          acc[SLOT_L1] += fabsf(n0 - nb0);
+          acc[SLOT_L1] += fabsf(n1 - nb1);
         }
         res[k * RW + c] = make_float2(n0 - 2.f * nb0, n1 - 2.f * nb1);
       }
@@ -236,9 +244,9 @@ __global__ __launch_bounds__(256) void k_row_g(RowParams p, GenParams gp) {
         float y0, y1;
         S::unpack(S::load_pair(g + 2 * k), y0, y1);
         const float2 cc = res[k * RW + c];
-        const float n0 = S::round(fminf(fmaxf(fmaf(p.sigma, cc.x, y0), -th), th));
-        const float n1 = S::round(fminf(fmaxf(fmaf(p.sigma, cc.y, y1), -th), th));
-        S::store2(g + 2 * k, n0, n1);
+        float n0 = clip(fmaf(p.sigma, cc.x, y0), th);
+        float n1 = clip(fmaf(p.sigma, cc.y, y1), th);
+        S::store_pair(g + 2 * k, S::round2(n0, n1));
         if constexpr (STATS) {
           const float d0 = n0 - y0, d1 = n1 - y1;
           acc[SLOT_DY2] += d0 * d0 + d1 * d1;
@@ -252,7 +260,7 @@ __global__ __launch_bounds__(256) void k_row_g(RowParams p, GenParams gp) {
     const float th = p.fw.thr[j];
     for (int e = lane; e < M * RW; e += 64) {
       const float2 c = res[e];
-      res[e] = make_float2(c.x - fminf(fmaxf(c.x, -th), th), c.y - fminf(fmaxf(c.y, -th), th));
+      res[e] = make_float2(c.x - clip(c.x, th), c.y - clip(c.y, th));
     }
   }
   if constexpr (MODE == ROW_R2C || MODE == ROW_PRIME || MODE == ROW_SOLVE || MODE == ROW_SHRINK || MODE == ROW_PD) {
@@ -261,7 +269,7 @@ __global__ __launch_bounds__(256) void k_row_g(RowParams p, GenParams gp) {
     if (emit) {
       fft_sync<SYNC_WAVE>();
       float2* other = res == b0 ? b1 : b0;
-      float2* Y = gfft<false, SYNC_WAVE, RW>(res, other, gp.prow, 64, lane, p.tw, 2);
+      float2* Y = gfft<false, SYNC_WAVE, RW>(res, other, gp.prow, 64, lane, row_sw_g(p.tw, n));
       int cb, pitch;
       long long off;
       plane_geom(p.lout, ch % p.lout.nf, cb, pitch, off);
@@ -318,7 +326,7 @@ __global__ __launch_bounds__(256) void k_colg_fwd(ColParams p, GenParams gp) {
   const long long strip = blockIdx.y * (long long)n * p.P + (long long)blockIdx.x * E;
   for (int e = threadIdx.x; e < E; e += 256) b0[e] = p.in[strip + e];
   __syncthreads();
-  float2* r = gfft<false, SYNC_BLOCK, kGW>(b0, b1, gp.pcol, 256, threadIdx.x, p.tw, 1);
+  float2* r = gfft<false, SYNC_BLOCK, kGW>(b0, b1, gp.pcol, 256, threadIdx.x, col_sw_g(p.tw, gp.n));
   const int M = n / 2;
   for (int e = threadIdx.x; e < E; e += 256)
     if (blockIdx.x * kGW + (e % kGW) <= M) p.out[strip + e] = r[e];
@@ -343,7 +351,7 @@ __global__ __launch_bounds__(256) void k_colg_syn(ColParams p, GenParams gp) {
       b0[e] = make_float2(bu[e].x * f * p.inv_n2, bu[e].y * f * p.inv_n2);
     }
     __syncthreads();
-    float2* r = gfft<true, SYNC_BLOCK, kGW>(b0, b1, gp.pcol, 256, threadIdx.x, p.tw, 1);
+    float2* r = gfft<true, SYNC_BLOCK, kGW>(b0, b1, gp.pcol, 256, threadIdx.x, col_sw_g(p.tw, gp.n));
     const int4 geo = stg.geo[i];
     float2* o = p.out + l * p.tl.ls + geo_off(geo) + (long long)(it.x - geo.x / kGW) * E;
     for (int e = threadIdx.x; e < E; e += 256)
@@ -356,7 +364,7 @@ __device__ void colg_finish(const ColParams& p, const GenParams& gp, float2* acc
   const int n = gp.n, E = n * kGW, M = n / 2;
   for (int e = threadIdx.x; e < E; e += 256) acc[e] = make_float2(acc[e].x * p.inv_n2, acc[e].y * p.inv_n2);
   __syncthreads();
-  float2* r = gfft<true, SYNC_BLOCK, kGW>(acc, b1, gp.pcol, 256, threadIdx.x, p.tw, 1);
+  float2* r = gfft<true, SYNC_BLOCK, kGW>(acc, b1, gp.pcol, 256, threadIdx.x, col_sw_g(p.tw, gp.n));
   float2* o = p.out + l * (long long)n * p.P + (long long)strip * E;
   for (int e = threadIdx.x; e < E; e += 256)
     if (strip * kGW + (e % kGW) <= M) o[e] = r[e];
@@ -382,7 +390,7 @@ __global__ __launch_bounds__(256) void k_colg_ana(ColParams p, GenParams gp) {
       b0[e] = k1 <= M ? in[e] : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    float2* r = gfft<false, SYNC_BLOCK, kGW>(b0, b1, gp.pcol, 256, threadIdx.x, p.tw, 1);
+    float2* r = gfft<false, SYNC_BLOCK, kGW>(b0, b1, gp.pcol, 256, threadIdx.x, col_sw_g(p.tw, gp.n));
     for (int e = threadIdx.x; e < E; e += 256) {
       const float f = psi_at_rt(p, stg.win[i][e % kGW], e / kGW, n);   // zero window past N/2
       ba[e] = make_float2(ba[e].x + r[e].x * f, ba[e].y + r[e].y * f);

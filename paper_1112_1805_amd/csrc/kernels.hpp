@@ -28,6 +28,7 @@ __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(
 __device__ __forceinline__ uint16_t f_to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t f2_to_bf16x2(float a, float b) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){a, b}, bf16x2_t));
 }
@@ -51,6 +52,9 @@ template <> struct Store<ST_F32> {
     *reinterpret_cast<float2*>(p) = make_float2(a, b);
   }
   __device__ __forceinline__ static float round(float a) { return a; }
+  // round a and b to the storage type in place; returns the stored pair
+  __device__ __forceinline__ static Pair round2(float& a, float& b) { return make_float2(a, b); }
+  __device__ __forceinline__ static void store_pair(T* p, Pair v) { *reinterpret_cast<float2*>(p) = v; }
   __device__ __forceinline__ static float to_float(T a) { return a; }
   __device__ __forceinline__ static T from_float(float a) { return a; }
 };
@@ -65,6 +69,13 @@ template <> struct Store<ST_BF16> {
     *reinterpret_cast<uint32_t*>(p) = f2_to_bf16x2(a, b);
   }
   __device__ __forceinline__ static float round(float a) { return bf16_to_f(f_to_bf16(a)); }
+  __device__ __forceinline__ static Pair round2(float& a, float& b) {
+    const uint32_t v = f2_to_bf16x2(a, b);
+    a = __uint_as_float(v << 16);
+    b = __uint_as_float(v & 0xffff0000u);
+    return v;
+  }
+  __device__ __forceinline__ static void store_pair(T* p, Pair v) { *reinterpret_cast<uint32_t*>(p) = v; }
   __device__ __forceinline__ static float to_float(T a) { return bf16_to_f(a); }
   __device__ __forceinline__ static T from_float(float a) { return f_to_bf16(a); }
 };
@@ -79,9 +90,20 @@ template <> struct Store<ST_F16> {
     *reinterpret_cast<uint32_t*>(p) = uint32_t(f_to_f16(a)) | (uint32_t(f_to_f16(b)) << 16);
   }
   __device__ __forceinline__ static float round(float a) { return f16_to_f(f_to_f16(a)); }
+  __device__ __forceinline__ static Pair round2(float& a, float& b) {
+    // one packed conversion (round to nearest even) for both values
+    const f16x2_t h = __builtin_convertvector((f32x2_t){a, b}, f16x2_t);
+    a = float(h[0]);
+    b = float(h[1]);
+    return __builtin_bit_cast(uint32_t, h);
+  }
+  __device__ __forceinline__ static void store_pair(T* p, Pair v) { *reinterpret_cast<uint32_t*>(p) = v; }
   __device__ __forceinline__ static float to_float(T a) { return f16_to_f(a); }
   __device__ __forceinline__ static T from_float(float a) { return f_to_f16(a); }
 };
+
+// x clipped to [-th, th] (th >= 0): one median-of-three instruction
+__device__ __forceinline__ float clip(float x, float th) { return __builtin_amdgcn_fmed3f(x, -th, th); }
 
 // ---------------------------------------------------------------- FP64 block reduction
 __device__ __forceinline__ double wave_sum(double v) {
@@ -299,6 +321,17 @@ template <int N> struct RowGeom {
   static constexpr int LROW = M + M / R;      // LDS float2 per row (padded)
 };
 
+// Twiddle tables of a power-of-two plan, one device array: [0, N) holds exp(-2 pi i m / N);
+// then the stage table of the row FFTs (length N/2), then that of the column FFTs
+// (length N).
+template <int N> constexpr int row_sw_off() { return N; }
+template <int N> constexpr int col_sw_off() {
+  return N + stage_tw_size<N / 2, RowGeom<N>::R, RowGeom<N>::RM>();
+}
+template <int N> constexpr int tw_table_size() {
+  return col_sw_off<N>() + stage_tw_size<N, ColGeom<N>::R, ColGeom<N>::RM>();
+}
+
 constexpr int kMaxFilters = 256;
 struct FilterWeights {
   float thr[kMaxFilters];   // per-filter threshold gamma * lambda_j
@@ -368,8 +401,9 @@ __device__ __forceinline__ void row_c2r(cpx (&a)[RowGeom<N>::R], const float2* _
   const PlaneBuf B(X, pitch * N);
   const int ip0 = t - cb, im0 = G::M - t - cb;
   const int op0 = tix<N>(ip0, row), om0 = tix<N>(im0, row);
-  // Chunk r covers k in [r T, r T + T) for every row of the wave; whether it meets the
-  // window (directly or mirrored) is uniform, so chunks outside it are skipped whole.
+  // Every bin outside the plane's columns maps below 0 or at or above pitch * N: its load
+  // is out of range and reads zero.  The loads are issued unconditionally (no per-chunk
+  // branch, no zero fill): they cost memory-pipe slots, which this VALU-bound pass has spare.
   cpx xp[G::R], xm[G::R];
   static_for<G::R>([&](auto r) {
     constexpr int k0 = r * G::T;
@@ -384,7 +418,7 @@ __device__ __forceinline__ void row_c2r(cpx (&a)[RowGeom<N>::R], const float2* _
     const cpx w = conj(ld(tw + k));          // W_N^{-k}
     a[r] = s + mul_i(cmul(d, w));
   });
-  fft_run<G::M, G::R, G::RM, true, SYNC_WAVE>(a, A, t, tw, 2);
+  fft_run<G::M, G::R, G::RM, true, SYNC_WAVE>(a, A, t, tw + row_sw_off<N>());
 }
 
 // Forward real FFT of a row held as pairs a[r] = (x[2p], x[2p+1]); writes the bins of
@@ -393,7 +427,7 @@ template <int N, class Addr>
 __device__ __forceinline__ void row_r2c(cpx (&a)[RowGeom<N>::R], float2* __restrict__ X, int row, int cb, int pitch,
                                         const Addr& A, int t, const float2* __restrict__ tw) {
   using G = RowGeom<N>;
-  fft_run<G::M, G::R, G::RM, false, SYNC_WAVE>(a, A, t, tw, 2);
+  fft_run<G::M, G::R, G::RM, false, SYNC_WAVE>(a, A, t, tw + row_sw_off<N>());
   const int tq = int(unsigned(t) / G::R), tr = int(unsigned(t) % G::R);
   fft_sync<SYNC_WAVE>();
   static_for<G::R>([&](auto r) { st(A.template at<G::R>(tq + r * G::RM, tr), a[r]); });
@@ -471,21 +505,24 @@ __global__ __launch_bounds__(256) void k_row(RowParams p) {
       const int k = t + r * G::T;
       float g0, g1;
       S::unpack(gv[r], g0, g1);
-      const float b0 = fminf(fmaxf(g0, -th), th), b1 = fminf(fmaxf(g1, -th), th);
+      const float b0 = clip(g0, th), b1 = clip(g1, th);
       float n0 = g0, n1 = g1;
       if constexpr (MODE == ROW_SOLVE) {
         // g <- clip(g) + S_j u  (v = shrink(g), b_v = clip(g); Section 3 v- and b_v-updates)
-        n0 = S::round(b0 + a[r].x);
-        n1 = S::round(b1 + a[r].y);
-        S::store2(gp + 2 * k, n0, n1);
+        n0 = b0 + a[r].x;
+        n1 = b1 + a[r].y;
+        S::store_pair(gp + 2 * k, S::round2(n0, n1));
       }
-      const float nb0 = fminf(fmaxf(n0, -th), th), nb1 = fminf(fmaxf(n1, -th), th);
+      const float nb0 = clip(n0, th), nb1 = clip(n1, th);
       if constexpr (STATS && MODE == ROW_SOLVE) {
         const float dv0 = (n0 - nb0) - (g0 - b0), dv1 = (n1 - nb1) - (g1 - b1);
         const float db0 = nb0 - b0, db1 = nb1 - b1;
-        acc[SLOT_DY2] += dv0 * dv0 + dv1 * dv1;
-        acc[SLOT_DB2] += db0 * db0 + db1 * db1;
-        acc[SLOT_L1] += fabsf(n0 - nb0) + fabsf(n1 - nb1);
+        acc[SLOT_DY2] = fmaf(dv0, dv0, acc[SLOT_DY2]);
+        acc[SLOT_DY2] = fmaf(dv1, dv1, acc[SLOT_DY2]);
+        acc[SLOT_DB2] = fmaf(db0, db0, acc[SLOT_DB2]);
+        acc[SLOT_DB2] = fmaf(db1, db1, acc[SLOT_DB2]);
+        acc[SLOT_L1] += fabsf(n0 - nb0);
+        acc[SLOT_L1] += fabsf(n1 - nb1);
       }
       // next adjoint input v - b_v = g - 2 clip(g)
       a[r] = cpx{n0 - 2.f * nb0, n1 - 2.f * nb1};
@@ -501,9 +538,9 @@ __global__ __launch_bounds__(256) void k_row(RowParams p) {
     static_for<G::R>([&](auto r) {
       float y0, y1;
       S::unpack(gv[r], y0, y1);
-      const float n0 = S::round(fminf(fmaxf(fmaf(p.sigma, a[r].x, y0), -th), th));
-      const float n1 = S::round(fminf(fmaxf(fmaf(p.sigma, a[r].y, y1), -th), th));
-      S::store2(gp + 2 * (t + r * G::T), n0, n1);
+      float n0 = clip(fmaf(p.sigma, a[r].x, y0), th);
+      float n1 = clip(fmaf(p.sigma, a[r].y, y1), th);
+      S::store_pair(gp + 2 * (t + r * G::T), S::round2(n0, n1));
       if constexpr (STATS) {
         const float d0 = n0 - y0, d1 = n1 - y1;
         acc[SLOT_DY2] += d0 * d0 + d1 * d1;
@@ -517,7 +554,7 @@ __global__ __launch_bounds__(256) void k_row(RowParams p) {
     // soft shrinkage of the coefficient row (Section 3's S_lambda, threshold thr_j)
     const float th = p.fw.thr[j];
     static_for<G::R>([&](auto r) {
-      a[r] = cpx{a[r].x - fminf(fmaxf(a[r].x, -th), th), a[r].y - fminf(fmaxf(a[r].y, -th), th)};
+      a[r] = cpx{a[r].x - clip(a[r].x, th), a[r].y - clip(a[r].y, th)};
     });
   }
   if constexpr (MODE == ROW_R2C || MODE == ROW_PRIME || MODE == ROW_SOLVE || MODE == ROW_SHRINK || MODE == ROW_PD) {
@@ -624,7 +661,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per
   const long long strip = l * (long long)N * p.P + (long long)blockIdx.x * (N * W) + c;
   cpx a[R];
   static_for<R>([&](auto r) { a[r] = valid ? ld(p.in + strip + (t + r * T) * W) : cpx{0.f, 0.f}; });
-  fft_run<N, R, G::RM, false, SYNC_BLOCK>(a, A, t, p.tw, 1);
+  fft_run<N, R, G::RM, false, SYNC_BLOCK>(a, A, t, p.tw + col_sw_off<N>());
   if (valid) {
     static_for<R>([&](auto r) { st(p.out + strip + (t + r * T) * W, a[r]); });
   }
@@ -657,7 +694,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per
     cpx a[R];
     static_for<R>([&](auto r) { a[r] = uh[r] * (ps[r] * p.inv_n2); });
     if (i + 1 < it.z) PB.load<N, R, T>(stg.win[i + 1][c], t, ps);
-    fft_run<N, R, G::RM, true, SYNC_BLOCK>(a, A, t, p.tw, 1);
+    fft_run<N, R, G::RM, true, SYNC_BLOCK>(a, A, t, p.tw + col_sw_off<N>());
     const int4 geo = stg.geo[i];
     float2* o = p.out + l * p.tl.ls + geo_off(geo) + (long long)(it.x - geo.x / W) * (N * W) + c;
     if (valid) {
@@ -672,7 +709,7 @@ __device__ __forceinline__ void col_finish(const ColParams& p, cpx (&acc)[ColCfg
   using G = ColCfg<N>;
   constexpr int R = G::R, T = G::T;
   static_for<R>([&](auto r) { acc[r] = acc[r] * p.inv_n2; });
-  fft_run<N, R, G::RM, true, SYNC_BLOCK>(acc, A, t, p.tw, 1);
+  fft_run<N, R, G::RM, true, SYNC_BLOCK>(acc, A, t, p.tw + col_sw_off<N>());
   float2* o = p.out + l * (long long)N * p.P + (long long)(k1 / G::W) * (N * G::W) + (k1 & (G::W - 1));
   if (valid) {
     static_for<R>([&](auto r) { st(o + (t + r * T) * G::W, acc[r]); });
@@ -718,7 +755,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per
     }
     float ps[R];
     PB.load<N, R, T>(stg.win[i][c], t, ps);
-    fft_run<N, R, G::RM, false, SYNC_BLOCK>(a, A, t, p.tw, 1);
+    fft_run<N, R, G::RM, false, SYNC_BLOCK>(a, A, t, p.tw + col_sw_off<N>());
     static_for<R>([&](auto r) { acc[r] = acc[r] + a[r] * ps[r]; });
   }
   if (it.w < 0) {

@@ -27,7 +27,7 @@ struct shs_plan {
   int rw;              // generic path: rows per wave of the row pass (1, 2 or 4)
   FftPlan prow, pcol;  // mixed-radix stage lists (generic path)
   float* psi;          // [eta][N][PP] dense filter bank (half spectrum)
-  float2* tw;          // [N] exp(-2 pi i m / N)
+  float2* tw;          // [N] exp(-2 pi i m / N), then (power-of-two N) the FFT stage tables
   float* eig;          // [N] 4 sin^2(pi k / N): DFT eigenvalues of one forward-difference pair (TV)
   // pruned layout
   float* psiw;         // filter values inside each column window
@@ -148,6 +148,48 @@ int by_size(int n) {
   return 0;
 }
 template <int N> struct RpbOf { static constexpr int value = RowGeom<N>::RPB; };
+
+// Stage twiddle table of fft_run<L, R, RM> (thread read order), copied from the base table
+// exp(-2 pi i m / NT) so both hold identical values.
+template <int L, int R, int RM>
+void fill_stage_tw(const std::vector<float2>& tw, int NT, float2* out) {
+  constexpr int T = L / R;
+  const int step = NT / L;
+  for (int r = 1; r < R; ++r)
+    for (int t = 0; t < T; ++t) out[(r - 1) * T + t] = tw[(r * t * step) % NT];
+  for (int r = 1; r < RM; ++r)
+    for (int tr = 0; tr < R; ++tr) out[(R - 1) * T + (r - 1) * R + tr] = tw[(r * tr * (L / (R * RM)) * step) % NT];
+}
+template <int N>
+void fill_plan_tw(std::vector<float2>& tw) {
+  tw.resize(tw_table_size<N>());
+  fill_stage_tw<N / 2, RowGeom<N>::R, RowGeom<N>::RM>(tw, N, tw.data() + row_sw_off<N>());
+  fill_stage_tw<N, ColGeom<N>::R, ColGeom<N>::RM>(tw, N, tw.data() + col_sw_off<N>());
+}
+// Stage table of a mixed-radix transform of length L (gstage): W_{Ns R}^{i k} at
+// i Ns + k - 1, copied from the base table of NT = L * step entries.
+void fill_stage_tw_g(const FftPlan& pl, const std::vector<float2>& tw, int NT, float2* out) {
+  const int L = pl.L, step = NT / L;
+  for (int e = 0; e < L; ++e) out[e] = tw[0];
+  int Ns = 1;
+  for (int s = 0; s < pl.ns; ++s) {
+    const int R = pl.radix[s];
+    for (int i = 1; i < R; ++i)
+      for (int k = 0; k < Ns; ++k)
+        if (Ns > 1) out[i * Ns + k - 1] = tw[(long long)i * k * (L / (Ns * R)) * step % NT];
+    Ns *= R;
+  }
+}
+void fill_stage_tables(int n, std::vector<float2>& tw) {
+  switch (n) {
+    case 64: fill_plan_tw<64>(tw); break;
+    case 128: fill_plan_tw<128>(tw); break;
+    case 256: fill_plan_tw<256>(tw); break;
+    case 512: fill_plan_tw<512>(tw); break;
+    case 1024: fill_plan_tw<1024>(tw); break;
+    case 2048: fill_plan_tw<2048>(tw); break;
+  }
+}
 template <int N> struct WOf { static constexpr int value = ColGeom<N>::W; };
 
 constexpr int kRed1Blocks = 256;
@@ -1009,12 +1051,20 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
   p->device = device;
   const size_t psi_bytes = size_t(p->eta) * n * p->PP * 4;
   if (hipMalloc(&p->psi, psi_bytes) != hipSuccess) { free_plan(p); return fail(SHS_E_NOMEM, "filter bank allocation"); }
-  if (hipMalloc(&p->tw, size_t(n) * 8) != hipSuccess) { free_plan(p); return fail(SHS_E_NOMEM, "twiddle allocation"); }
   std::vector<float2> tw(n);
   for (int m = 0; m < n; ++m) {
     const double a = -2.0 * M_PI * double(m) / double(n);
     tw[m] = make_float2(float(std::cos(a)), float(std::sin(a)));
   }
+  // append the row and column stage tables
+  if (pow2) {
+    fill_stage_tables(n, tw);
+  } else {
+    tw.resize(size_t(n) + n / 2 + n);
+    fill_stage_tw_g(prow, tw, n, tw.data() + n);
+    fill_stage_tw_g(pcol, tw, n, tw.data() + n + n / 2);
+  }
+  if (hipMalloc(&p->tw, tw.size() * 8) != hipSuccess) { free_plan(p); return fail(SHS_E_NOMEM, "twiddle allocation"); }
   std::vector<float> eig(n);
   for (int k = 0; k < n; ++k) {
     const double sn = std::sin(M_PI * double(k) / double(n));
@@ -1022,7 +1072,7 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
   }
   if (hipMalloc(&p->eig, size_t(n) * 4) != hipSuccess) { free_plan(p); return fail(SHS_E_NOMEM, "eigenvalue table"); }
   if (hipMemcpy(p->eig, eig.data(), size_t(n) * 4, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(p->tw, tw.data(), size_t(n) * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(p->psi, 0, psi_bytes) != hipSuccess) {
     free_plan(p);
     return fail(SHS_E_DEVICE, "plan initialisation copy");

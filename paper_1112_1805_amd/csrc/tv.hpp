@@ -202,10 +202,10 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per
   const long long strip = l * (long long)N * p.P + (long long)blockIdx.x * (N * W) + c;
   cpx a[R];
   static_for<R>([&](auto r) { a[r] = valid ? ld(p.in + strip + (t + r * T) * W) : cpx{0.f, 0.f}; });
-  fft_run<N, R, G::RM, false, SYNC_BLOCK>(a, A, t, p.tw, 1);
+  fft_run<N, R, G::RM, false, SYNC_BLOCK>(a, A, t, p.tw + col_sw_off<N>());
   const float e1 = valid ? eig[k1] : 0.f;
   static_for<R>([&](auto r) { a[r] = a[r] * (p.inv_n2 / (1.f + eig[t + r * T] + e1)); });
-  fft_run<N, R, G::RM, true, SYNC_BLOCK>(a, A, t, p.tw, 1);
+  fft_run<N, R, G::RM, true, SYNC_BLOCK>(a, A, t, p.tw + col_sw_off<N>());
   if (valid) {
     static_for<R>([&](auto r) { st(p.out + strip + (t + r * T) * W, a[r]); });
   }
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void k_colg_solve(ColParams p, GenParams gp, c
   const long long strip = blockIdx.y * (long long)n * p.P + (long long)blockIdx.x * E;
   for (int e = threadIdx.x; e < E; e += 256) b0[e] = p.in[strip + e];
   __syncthreads();
-  float2* r = gfft<false, SYNC_BLOCK, kGW>(b0, b1, gp.pcol, 256, threadIdx.x, p.tw, 1);
+  float2* r = gfft<false, SYNC_BLOCK, kGW>(b0, b1, gp.pcol, 256, threadIdx.x, col_sw_g(p.tw, gp.n));
   float2* o = r == b0 ? b1 : b0;
   for (int e = threadIdx.x; e < E; e += 256) {
     const int k1 = blockIdx.x * kGW + (e % kGW);
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(256) void k_colg_solve(ColParams p, GenParams gp, c
     r[e] = make_float2(r[e].x * m, r[e].y * m);
   }
   __syncthreads();
-  float2* z = gfft<true, SYNC_BLOCK, kGW>(r, o, gp.pcol, 256, threadIdx.x, p.tw, 1);
+  float2* z = gfft<true, SYNC_BLOCK, kGW>(r, o, gp.pcol, 256, threadIdx.x, col_sw_g(p.tw, gp.n));
   for (int e = threadIdx.x; e < E; e += 256)
     if (blockIdx.x * kGW + (e % kGW) <= M) p.out[strip + e] = z[e];
 }
