@@ -189,14 +189,23 @@ struct RowAddr {
     return base + (q * (R + 1) + rr);
   }
 };
-// Column style: W FFTs interleaved, point pos of FFT c at pos*W + c.
-template <int W>
+// Column style: W FFTs interleaved, point pos of FFT c at (pos + pos/R)*W + c.  The pad
+// slot every R points keeps the first stage's writes (lane stride R points) off a single
+// bank group: without it a stride of R*W*8 bytes, a multiple of the 256-byte bank width,
+// sends every lane of a column to the same banks.
+template <int W, int R>
 struct ColAddr {
   float2* base;  // already offset by the column c
-  __device__ __forceinline__ float2* operator()(unsigned pos) const { return base + pos * W; }
+  __device__ __forceinline__ float2* operator()(unsigned pos) const { return base + (pos + pos / R) * W; }
   template <int RQ>
-  __device__ __forceinline__ float2* at(int q, int rr) const { return base + (q * RQ + rr) * W; }
+  __device__ __forceinline__ float2* at(int q, int rr) const {
+    static_assert(RQ == R, "column addressing pads every R points");
+    return base + (q * (R + 1) + rr) * W;
+  }
 };
+// LDS points (per column) of a padded column FFT of length L with radix R.
+template <int L, int R>
+constexpr int col_lds_points() { return L + L / R; }
 
 // Inter-stage twiddles of one FFT configuration, stored in the order the threads read
 // them so that the lanes of a wave load consecutive entries (a table indexed by the

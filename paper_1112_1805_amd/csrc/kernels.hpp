@@ -652,12 +652,12 @@ template <int N>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_col_fwd(ColParams p) {
   using G = ColCfg<N>;
   constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
-  __shared__ float2 lds[N * W];
+  __shared__ float2 lds[col_lds_points<N, R>() * W];
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int k1 = blockIdx.x * W + c;
   const bool valid = k1 <= M;
   const int l = blockIdx.y;
-  const ColAddr<W> A{lds + c};
+  const ColAddr<W, R> A{lds + c};
   const long long strip = l * (long long)N * p.P + (long long)blockIdx.x * (N * W) + c;
   cpx a[R];
   static_for<R>([&](auto r) { a[r] = valid ? ld(p.in + strip + (t + r * T) * W) : cpx{0.f, 0.f}; });
@@ -674,14 +674,14 @@ template <int N>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(ColGeom<N>::WPE))) void k_col_syn(ColParams p) {
   using G = ColCfg<N>;
   constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
-  __shared__ float2 lds[N * W];
+  __shared__ float2 lds[col_lds_points<N, R>() * W];
   __shared__ ItemStage<W> stg;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int4 it = p.items[blockIdx.x];
   const int k1 = it.x * W + c;
   const bool valid = k1 <= M;
   const int l = blockIdx.y;
-  const ColAddr<W> A{lds + c};
+  const ColAddr<W, R> A{lds + c};
   stage_item<N>(p, it, stg);
   cpx uh[R];
   const float2* U = p.in + l * (long long)N * p.P + (long long)it.x * (N * W) + c;
@@ -705,7 +705,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per
 
 template <int N>
 __device__ __forceinline__ void col_finish(const ColParams& p, cpx (&acc)[ColCfg<N>::R], int t, int k1, bool valid,
-                                           int l, const ColAddr<ColCfg<N>::W>& A) {
+                                           int l, const ColAddr<ColCfg<N>::W, ColCfg<N>::R>& A) {
   using G = ColCfg<N>;
   constexpr int R = G::R, T = G::T;
   static_for<R>([&](auto r) { acc[r] = acc[r] * p.inv_n2; });
@@ -724,14 +724,14 @@ template <int N>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(ColGeom<N>::WPE))) void k_col_ana(ColParams p) {
   using G = ColCfg<N>;
   constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
-  __shared__ float2 lds[N * W];
+  __shared__ float2 lds[col_lds_points<N, R>() * W];
   __shared__ ItemStage<W> stg;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int4 it = p.items[blockIdx.x];
   const int k1 = it.x * W + c;
   const bool valid = k1 <= M;
   const int l = blockIdx.y;
-  const ColAddr<W> A{lds + c};
+  const ColAddr<W, R> A{lds + c};
   stage_item<N>(p, it, stg);
   __syncthreads();
   // T2 column of item filter i; columns past N/2 are never written and read as zero
@@ -770,14 +770,14 @@ template <int N>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_col_final(ColParams p) {
   using G = ColCfg<N>;
   constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
-  __shared__ float2 lds[N * W];
+  __shared__ float2 lds[col_lds_points<N, R>() * W];
   const int2 si = p.strips[blockIdx.x];
   if (si.y <= 1) return;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int k1 = blockIdx.x * W + c;
   const bool valid = k1 <= M;
   const int l = blockIdx.y;
-  const ColAddr<W> A{lds + c};
+  const ColAddr<W, R> A{lds + c};
   cpx acc[R];
   static_for<R>([&](auto r) { acc[r] = cpx{0.f, 0.f}; });
   for (int i = 0; i < si.y; ++i) {

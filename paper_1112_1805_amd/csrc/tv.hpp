@@ -193,12 +193,12 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per
     ColParams p, const float* __restrict__ eig) {
   using G = ColCfg<N>;
   constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
-  __shared__ float2 lds[N * W];
+  __shared__ float2 lds[col_lds_points<N, R>() * W];
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int k1 = blockIdx.x * W + c;
   const bool valid = k1 <= M;
   const int l = blockIdx.y;
-  const ColAddr<W> A{lds + c};
+  const ColAddr<W, R> A{lds + c};
   const long long strip = l * (long long)N * p.P + (long long)blockIdx.x * (N * W) + c;
   cpx a[R];
   static_for<R>([&](auto r) { a[r] = valid ? ld(p.in + strip + (t + r * T) * W) : cpx{0.f, 0.f}; });
