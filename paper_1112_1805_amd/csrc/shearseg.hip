@@ -333,6 +333,8 @@ Ops ops_for() {
   return Ops{&Pipe<N>::row, &Pipe<N>::col};
 }
 
+constexpr int kGenericMaxN = 1024;   // largest image side of the mixed-radix path
+
 // Stage list of a mixed-radix transform of length L (radices 16, 8, 4, 2, 9, 3 and the
 // primes 5..23); false if L has a larger prime factor.
 bool make_fft_plan(int L, FftPlan& pl) {
@@ -1022,7 +1024,7 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
   const bool pow2 = get_ops_pow2(n, o);
   if (!pow2) {
     // mixed-radix path: N a multiple of 8 in [64, 1024] whose prime factors are <= 23
-    if (n % 8 != 0 || n < 64 || n > 1024 || !make_fft_plan(n / 2, prow) || !make_fft_plan(n, pcol))
+    if (n % 8 != 0 || n < 64 || n > kGenericMaxN || !make_fft_plan(n / 2, prow) || !make_fft_plan(n, pcol))
       return fail(SHS_E_UNSUPPORTED,
                   "n must be a power of two in 64..2048 or a multiple of 8 in 64..1024 with prime factors <= 23");
   }
@@ -1085,9 +1087,10 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
     return fail(SHS_E_DEVICE, "filter generation failed");
   }
   if (p->generic) {
-    // generic column passes hold 3 strips of N x 4 bins in dynamic LDS (up to 96 KB)
-    const int lds3 = 3 * n * kGW * int(sizeof(float2));
-    const int lds2 = 2 * n * kGW * int(sizeof(float2));
+    // generic column passes hold 3 strips of N x 4 bins in dynamic LDS (up to 96 KB); the
+    // cap is set for the largest supported N, so plans of any size can be created in any order
+    const int lds3 = 3 * kGenericMaxN * kGW * int(sizeof(float2));
+    const int lds2 = 2 * kGenericMaxN * kGW * int(sizeof(float2));
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colg_syn), hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds3) != hipSuccess ||
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colg_ana), hipFuncAttributeMaxDynamicSharedMemorySize,
