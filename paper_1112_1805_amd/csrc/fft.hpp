@@ -207,6 +207,24 @@ struct ColAddr {
 template <int L, int R>
 constexpr int col_lds_points() { return L + L / R; }
 
+// The Q - 1 twiddles w[r] = z^r (1 <= r < Q, Q a power of two) of one butterfly: the
+// powers z^1, z^2, z^4, z^8 are loaded (entry (r-1)*stride of `p`), the others are
+// products of two of them (at most three roundings from the table values).  Loads go
+// through the vector-memory data path, which the row pass saturates; the products cost
+// a few FMAs each.
+template <int Q>
+__device__ __forceinline__ void pow2_twiddles(const float2* __restrict__ p, int stride, cpx (&w)[Q]) {
+  static_for<Q>([&](auto r) {
+    if constexpr (r > 0 && (r & (r - 1)) == 0) w[r] = ld(p + (r - 1) * stride);
+  });
+  static_for<Q>([&](auto r) {
+    if constexpr (r > 0 && (r & (r - 1)) != 0) {
+      constexpr int hi = 1 << (31 - __builtin_clz(unsigned(r)));
+      w[r] = cmul(w[hi], w[r - hi]);
+    }
+  });
+}
+
 // Inter-stage twiddles of one FFT configuration, stored in the order the threads read
 // them so that the lanes of a wave load consecutive entries (a table indexed by the
 // exponent r*t would be read with stride r and touch up to one cache line per lane):
@@ -242,9 +260,7 @@ __device__ __forceinline__ void fft_run(cpx (&a)[R], const Addr& lds, int t, con
     });
     fft_sync<SK>();
     cpx w[RM];
-    static_for<RM>([&](auto r) {
-      if constexpr (r > 0) w[r] = ld(sw + ((R - 1) * T + (r - 1) * R) + tr);
-    });
+    pow2_twiddles<RM>(sw + (R - 1) * T + tr, R, w);
     static_for<U>([&](auto u) {
       cpx c[RM];
       static_for<RM>([&](auto r) {
@@ -259,10 +275,12 @@ __device__ __forceinline__ void fft_run(cpx (&a)[R], const Addr& lds, int t, con
     fft_sync<SK>();
   }
   // last stage: radix R, Ns = L/R, butterfly bf = t; input t + r*T = (tq + r*RM) * R + tr
+  cpx wl[R];
+  pow2_twiddles<R>(sw + t, T, wl);
   static_for<R>([&](auto r) {
     cpx v = ld(lds.template at<R>(tq + r * RM, tr));
     if constexpr (r > 0) {
-      cpx w = ld(sw + (r - 1) * T + t);
+      const cpx w = wl[r];
       v = INV ? cmulc(v, w) : cmul(v, w);
     }
     a[r] = v;

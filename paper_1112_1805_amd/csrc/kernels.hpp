@@ -412,10 +412,11 @@ __device__ __forceinline__ void row_c2r(cpx (&a)[RowGeom<N>::R], const float2* _
     if (k0 < cb + pitch && k0 + G::T > cb) xp[r] = B.load(row_bin<N, 1>(ip0, op0, r, row));
     if (k0 <= G::M - cb && k0 + G::T > G::M - cb - pitch) xm[r] = B.load(row_bin<N, -1>(im0, om0, r, row));
   });
+  // W_N^k for k = t + r T as W_N^t times the compile-time constant W_N^{r T}: one load
+  const cpx w0 = ld(tw + t);
   static_for<G::R>([&](auto r) {
-    const int k = t + r * G::T;
     const cpx s = xp[r] + conj(xm[r]), d = xp[r] - conj(xm[r]);
-    const cpx w = conj(ld(tw + k));          // W_N^{-k}
+    const cpx w = conj(twc<r * G::T, N, false>(w0));   // W_N^{-k}
     a[r] = s + mul_i(cmul(d, w));
   });
   fft_run<G::M, G::R, G::RM, true, SYNC_WAVE>(a, A, t, tw + row_sw_off<N>());
@@ -434,6 +435,7 @@ __device__ __forceinline__ void row_r2c(cpx (&a)[RowGeom<N>::R], float2* __restr
   fft_sync<SYNC_WAVE>();
   const PlaneBuf B(X, pitch * N);
   const int ip0 = t - cb, op0 = tix<N>(ip0, row);
+  const cpx w0 = ld(tw + t);
   static_for<G::R>([&](auto r) {
     constexpr int k0 = r * G::T;
     if (k0 < cb + pitch && k0 + G::T > cb) {
@@ -441,7 +443,7 @@ __device__ __forceinline__ void row_r2c(cpx (&a)[RowGeom<N>::R], float2* __restr
       const cpx yk = a[r];
       const cpx ym = conj(ld(A(unsigned(G::M - k) & unsigned(G::M - 1))));
       const cpx s = yk + ym, d = yk - ym;
-      const cpx w = ld(tw + k);                 // W_N^{k}
+      const cpx w = twc<r * G::T, N, false>(w0);   // W_N^{k}
       B.store(row_bin<N, 1>(ip0, op0, r, row), (s - mul_i(cmul(d, w))) * 0.5f);
     }
   });
