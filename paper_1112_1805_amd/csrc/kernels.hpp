@@ -241,14 +241,15 @@ __global__ void k_datacost(const float* __restrict__ img, int C, Codebook cb, in
 // those <= N/2 exist).  Strips are stored as contiguous blocks, so W only trades block
 // size against occupancy (W = 4 at N = 1024: 256 threads, 32 KB LDS, 3 blocks per CU).
 // WPE is the occupancy hint of the filtered column passes (waves per SIMD).  At N = 2048
-// they run at two waves and load the next filter's spectrum column during the current
-// FFT (PREFETCH); at three waves that extra register set would spill.
+// they run at two waves and load the next filter's spectrum column and filter values
+// during the current FFT (PREFETCH); with more waves per SIMD those extra registers would
+// spill.
 template <int N> struct ColGeom;
 template <> struct ColGeom<64>   { static constexpr int R = 8,  RM = 1, W = 16, WPE = 3; };
 template <> struct ColGeom<128>  { static constexpr int R = 8,  RM = 2, W = 16, WPE = 3; };
 template <> struct ColGeom<256>  { static constexpr int R = 16, RM = 1, W = 16, WPE = 3; };
 template <> struct ColGeom<512>  { static constexpr int R = 16, RM = 2, W = 8,  WPE = 3; };
-template <> struct ColGeom<1024> { static constexpr int R = 16, RM = 4, W = 4,  WPE = 3; };
+template <> struct ColGeom<1024> { static constexpr int R = 16, RM = 4, W = 4,  WPE = 4; };
 template <> struct ColGeom<2048> { static constexpr int R = 16, RM = 8, W = 4,  WPE = 2; };
 template <int N> struct ColCfg : ColGeom<N> {
   static constexpr int T = N / ColGeom<N>::R;
@@ -670,8 +671,8 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per
 }
 
 // Synthesis: for every filter j of the item, T1[l, j] = colIFFT(psi_j * U_l / N^2) on the
-// item's strip (only columns inside filter j's range exist in T1).  The next filter's
-// values are loaded while the current inverse FFT runs.
+// item's strip (only columns inside filter j's range exist in T1).  With PREFETCH the next
+// filter's values are loaded while the current inverse FFT runs.
 template <int N>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(ColGeom<N>::WPE))) void k_col_syn(ColParams p) {
   using G = ColCfg<N>;
@@ -691,11 +692,14 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per
   __syncthreads();
   const PsiBuf PB(p);
   float ps[R];
-  PB.load<N, R, T>(stg.win[0][c], t, ps);
+  if constexpr (G::PREFETCH) PB.load<N, R, T>(stg.win[0][c], t, ps);
   for (int i = 0; i < it.z; ++i) {
+    if constexpr (!G::PREFETCH) PB.load<N, R, T>(stg.win[i][c], t, ps);
     cpx a[R];
     static_for<R>([&](auto r) { a[r] = uh[r] * (ps[r] * p.inv_n2); });
-    if (i + 1 < it.z) PB.load<N, R, T>(stg.win[i + 1][c], t, ps);
+    if constexpr (G::PREFETCH) {
+      if (i + 1 < it.z) PB.load<N, R, T>(stg.win[i + 1][c], t, ps);
+    }
     fft_run<N, R, G::RM, true, SYNC_BLOCK>(a, A, t, p.tw + col_sw_off<N>());
     const int4 geo = stg.geo[i];
     float2* o = p.out + l * p.tl.ls + geo_off(geo) + (long long)(it.x - geo.x / W) * (N * W) + c;
