@@ -7,6 +7,10 @@ multiplier updates, FP64 residual reductions every iteration), the label-map epi
 the exact final energy.  Inputs are resident in HBM before the timed region; the plan
 (filter bank) is built once before it.
 
+Inside the timed region only the dominant kernel is bracketed by HIP events (on its own
+launch stream) for the roofline figure; `kernel_breakdown_ms` comes from one more step run
+after the timed region with every library launch event-timed.
+
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -58,6 +62,18 @@ def describe(w, store, iters):
             f"FP32 FFT math, FP64 reductions")
 
 
+def profiled_breakdown(pkg, torch, fn):
+    """Per-class kernel times of one extra call of fn, outside the timed region, with every
+    library launch bracketed by HIP events (the timed region itself times only the dominant
+    kernel: each event pair is a command on the launch stream)."""
+    pkg.shs_profile_begin()
+    fn()
+    torch.cuda.synchronize()
+    prof = pkg.shs_profile_end()
+    return {k: {"launches": n, "total_ms": round(ms, 4), "avg_ms": round(ms / max(n, 1), 5)}
+            for k, (n, ms) in prof.items()}
+
+
 def read_traffic(kernel_hash: str):
     """Counter-measured HBM bytes per launch of the row_solve kernel, if the committed
     summary was taken on the current kernel sources."""
@@ -71,7 +87,9 @@ def read_traffic(kernel_hash: str):
     return float(mb.group(1))
 
 
-def run_gpu(args, w, store, iters, steps, warmup, profile):
+def run_gpu(args, w, store, iters, steps, warmup, profile, breakdown=False):
+    """profile: None/False (no event timing) or the kernel classes event-timed inside the
+    timed region; breakdown: afterwards, one more step with every class timed."""
     import torch
     import paper_1112_1805_amd as pkg
     dev = torch.device("cuda:0")
@@ -96,7 +114,7 @@ def run_gpu(args, w, store, iters, steps, warmup, profile):
         log(f"warmup {i + 1}/{warmup} done ({store})")
     torch.cuda.synchronize()
     if profile:
-        pkg.shs_profile_begin()
+        pkg.shs_profile_begin(profile)
     t0 = time.perf_counter()
     for i in range(steps):
         stats = step()
@@ -104,7 +122,8 @@ def run_gpu(args, w, store, iters, steps, warmup, profile):
     dt = time.perf_counter() - t0
     prof = pkg.shs_profile_end() if profile else None
     log(f"timed {steps} steps ({store}): {dt:.3f}s")
-    return dict(seconds=dt, plan_ms=plan_ms, stats=stats, prof=prof, ws_bytes=plan.workspace_bytes(),
+    bd = profiled_breakdown(pkg, torch, step) if (profile and breakdown) else None
+    return dict(seconds=dt, plan_ms=plan_ms, stats=stats, prof=prof, breakdown=bd, ws_bytes=plan.workspace_bytes(),
                 eta=plan.eta, labels=labels, u=u)
 
 
@@ -205,13 +224,14 @@ def run_denoise(args):
         plan.shearlet_denoise(f, lam, ws, out=out)
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done (denoise)")
-    pkg.shs_profile_begin()
+    pkg.shs_profile_begin(["row_shrink"])
     t0 = time.perf_counter()
     for _ in range(args.steps):
         plan.shearlet_denoise(f, lam, ws, out=out)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = pkg.shs_profile_end()
+    breakdown = profiled_breakdown(pkg, torch, lambda: plan.shearlet_denoise(f, lam, ws, out=out))
     ips = args.steps * count / dt
     eta = plan.eta
     # quality on the synthetic truth (sanity, not a benchmark figure)
@@ -241,8 +261,7 @@ def run_denoise(args):
                    "images": count, "filters": eta},
         "mpixel_filter_per_s": round(ips * n * n * eta / 1e6, 1),
         "roofline": roofline,
-        "kernel_breakdown_ms": {k: {"launches": v[0], "total_ms": round(v[1], 4), "avg_ms": round(v[1] / v[0], 5)}
-                                for k, v in prof.items()},
+        "kernel_breakdown_ms": breakdown,
         "psnr_db": {"noisy": psnr(f), "denoised": psnr(out)},
         "setup_ms": round(setup_ms, 1),
         "source_hash": source_hash(),
@@ -295,13 +314,14 @@ def run_pd(args):
         step()
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done (pd)")
-    pkg.shs_profile_begin()
+    pkg.shs_profile_begin(["row_pd"])
     t0 = time.perf_counter()
     for _ in range(args.steps):
         st = step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = pkg.shs_profile_end()
+    breakdown = profiled_breakdown(pkg, torch, step)
     its = args.steps * iters / dt
     eta = plan.eta
     sb = {"f32": 4, "bf16": 2, "f16": 2}[store]
@@ -321,8 +341,7 @@ def run_pd(args):
         "mpixel_label_filter_per_s": round(its * w.n * w.n * w.q * eta / 1e6, 1),
         "ms_per_iter": round(dt / args.steps / iters * 1e3, 4),
         "roofline": roofline,
-        "kernel_breakdown_ms": {k: {"launches": v[0], "total_ms": round(v[1], 4), "avg_ms": round(v[1] / v[0], 5)}
-                                for k, v in prof.items()},
+        "kernel_breakdown_ms": breakdown,
         "final_stats": {k: (round(v, 9) if isinstance(v, float) else v) for k, v in st.items()},
         "plan_create_ms": round(plan_ms, 2),
         "source_hash": source_hash(),
@@ -371,13 +390,14 @@ def run_tv(args):
         step()
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done (tv)")
-    pkg.shs_profile_begin()
+    pkg.shs_profile_begin(["tv_update"])
     t0 = time.perf_counter()
     for _ in range(args.steps):
         st = step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = pkg.shs_profile_end()
+    breakdown = profiled_breakdown(pkg, torch, step)
     its = args.steps * iters / dt
     sb = {"f32": 4, "bf16": 2, "f16": 2}[store]
     n2 = w.n * w.n
@@ -398,8 +418,7 @@ def run_tv(args):
                      "frac": round(amount / avg_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "tv_update", "algorithmic_per_launch": amount,
                      "avg_launch_ms": round(avg_s * 1e3, 5)},
-        "kernel_breakdown_ms": {k: {"launches": v[0], "total_ms": round(v[1], 4), "avg_ms": round(v[1] / v[0], 5)}
-                                for k, v in prof.items()},
+        "kernel_breakdown_ms": breakdown,
         "final_stats": {k: (round(v, 9) if isinstance(v, float) else v) for k, v in st.items()},
         "source_hash": source_hash(),
     }
@@ -448,13 +467,14 @@ def run_nl(args):
         step()
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done (nl)")
-    pkg.shs_profile_begin()
+    pkg.shs_profile_begin(["nl_dual"])
     t0 = time.perf_counter()
     for _ in range(args.steps):
         st = step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = pkg.shs_profile_end()
+    breakdown = profiled_breakdown(pkg, torch, step)
     its = args.steps * iters / dt
     sb = {"f32": 4, "bf16": 2, "f16": 2}[store]
     n2, M2 = w.n * w.n, nbr.shape[0]
@@ -475,8 +495,7 @@ def run_nl(args):
         "roofline": {"bound": "hbm", "achieved": round(amount / avg_s / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(amount / avg_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "nl_dual",
                      "algorithmic_per_launch": amount, "avg_launch_ms": round(avg_s * 1e3, 5)},
-        "kernel_breakdown_ms": {k: {"launches": v[0], "total_ms": round(v[1], 4), "avg_ms": round(v[1] / v[0], 5)}
-                                for k, v in prof.items()},
+        "kernel_breakdown_ms": breakdown,
         "final_stats": {k: (round(v, 9) if isinstance(v, float) else v) for k, v in st.items()},
         "source_hash": source_hash(),
     }
@@ -561,7 +580,7 @@ def main():
     store_bytes = 4 if args.store == "f32" else 2
     log(f"workload {w.name} n={w.n} q={w.q} J={w.J} iters={iters} store={args.store}")
 
-    main_run = run_gpu(args, w, args.store, iters, args.steps, args.warmup, profile=True)
+    main_run = run_gpu(args, w, args.store, iters, args.steps, args.warmup, profile=["row_solve"], breakdown=True)
     eta = main_run["eta"]
     sec = main_run["seconds"]
     its = args.steps * iters / sec
@@ -570,8 +589,7 @@ def main():
     # ---- roofline of the dominant kernel (event-timed inside the timed region)
     prof = main_run["prof"]
     units = kernel_units(w, iters, eta, store_bytes)
-    breakdown = {k: {"launches": n, "total_ms": round(ms, 4), "avg_ms": round(ms / max(n, 1), 5)}
-                 for k, (n, ms) in prof.items()}
+    breakdown = main_run["breakdown"]
     dominant = max((k for k in prof if k in units), key=lambda k: prof[k][1])
     bound, amount, unit = units[dominant]
     n_launch, tot_ms = prof[dominant]
@@ -625,7 +643,7 @@ def main():
     }
 
     if not args.no_f32 and args.store != "f32":
-        f32 = run_gpu(args, w, "f32", iters, 1, 1, profile=False)
+        f32 = run_gpu(args, w, "f32", iters, 1, 1, profile=None)
         f32_its = iters / f32["seconds"]
         agree = float((f32["labels"] == main_run["labels"]).float().mean().item())
         du = float((f32["u"] - main_run["u"]).abs().max().item())

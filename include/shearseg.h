@@ -288,13 +288,18 @@ shs_status shs_solve_batch(shs_batch* batch, const shs_params* params, const flo
  * bracketed by a pair of HIP events recorded on the stream it is launched on.
  * shs_profile_end() waits for those events and returns, per kernel class, the number of
  * launches and the summed event-measured duration; it returns the number of classes
- * written (<= max_entries) or -1 on error.  Process-wide; not for concurrent solves. */
+ * written (<= max_entries) or -1 on error.  Process-wide; not for concurrent solves.
+ * shs_profile_begin_classes(list) times only the kernel classes named in the
+ * comma-separated list (NULL or "" = all, as shs_profile_begin); each event pair sits on
+ * the launch stream, so timing fewer classes disturbs the stream less.  An unknown name
+ * returns SHS_E_INVALID and leaves the profiling state unchanged. */
 typedef struct {
   char name[32];       /* kernel class: row_solve, col_syn, col_ana, col_final, row_c2r, ... */
   int64_t launches;
   double total_ms;
 } shs_kernel_time;
 shs_status shs_profile_begin(void);
+shs_status shs_profile_begin_classes(const char* classes);
 int32_t shs_profile_end(shs_kernel_time* out, int32_t max_entries);
 
 const char* shs_status_str(shs_status status);

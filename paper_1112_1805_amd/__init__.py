@@ -98,6 +98,7 @@ _SIGS = {
     "shs_solve_batch": (_I32, [_VP, ctypes.POINTER(ShsParams), ctypes.POINTER(_VP), _VP, _SZ,
                                ctypes.POINTER(_VP), ctypes.POINTER(_VP), _VP, _VP]),
     "shs_profile_begin": (_I32, []),
+    "shs_profile_begin_classes": (_I32, [ctypes.c_char_p]),
     "shs_profile_end": (_I32, [ctypes.POINTER(ShsKernelTime), _I32]),
     "shs_status_str": (ctypes.c_char_p, [_I32]),
     "shs_last_error": (ctypes.c_char_p, []),
@@ -178,8 +179,14 @@ def shs_num_filters(J: int) -> int:
     return lib().shs_num_filters(J)
 
 
-def shs_profile_begin() -> None:
-    _check(lib().shs_profile_begin(), "shs_profile_begin")
+def shs_profile_begin(classes=None) -> None:
+    """Time every library kernel launch (classes=None) or only the named kernel classes
+    (an iterable of names such as "row_solve", or one comma-separated string)."""
+    if classes is None:
+        _check(lib().shs_profile_begin(), "shs_profile_begin")
+    else:
+        csv = classes if isinstance(classes, str) else ",".join(classes)
+        _check(lib().shs_profile_begin_classes(csv.encode()), "shs_profile_begin_classes")
 
 
 def shs_profile_end() -> dict:

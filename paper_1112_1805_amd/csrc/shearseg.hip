@@ -94,6 +94,7 @@ const char* const kKClassName[KC_COUNT] = {"row_solve", "col_syn", "col_ana", "c
 struct Prof {
   std::mutex mu;
   bool on = false;
+  uint32_t mask = ~0u;                 // kernel classes that are timed (bit per class)
   std::vector<hipEvent_t> pool;        // reused across sessions
   size_t used = 0;
   std::vector<int> cls;                // class of event pair i (events 2i, 2i+1)
@@ -115,7 +116,7 @@ struct Timed {
   hipEvent_t stop = nullptr;
   Timed(hipStream_t s_, int cls) : s(s_) {
     Prof& P = prof();
-    if (!P.on || g_capturing) return;
+    if (!P.on || g_capturing || !((P.mask >> cls) & 1u)) return;
     std::lock_guard<std::mutex> g(P.mu);
     while (P.pool.size() < P.used + 2) {
       hipEvent_t e;
@@ -969,10 +970,29 @@ const char* shs_status_str(shs_status s) {
 
 const char* shs_last_error(void) { return g_err.c_str(); }
 
-shs_status shs_profile_begin(void) {
+shs_status shs_profile_begin(void) { return shs_profile_begin_classes(nullptr); }
+
+shs_status shs_profile_begin_classes(const char* classes) {
+  uint32_t mask = 0;
+  if (!classes || !*classes) {
+    mask = ~0u;
+  } else {
+    std::string list(classes);
+    size_t pos = 0;
+    while (pos <= list.size()) {
+      const size_t end = std::min(list.find(',', pos), list.size());
+      const std::string name = list.substr(pos, end - pos);
+      int c = 0;
+      while (c < KC_COUNT && name != kKClassName[c]) ++c;
+      if (c == KC_COUNT) return fail(SHS_E_INVALID, "unknown kernel class '" + name + "'");
+      mask |= 1u << c;
+      pos = end + 1;
+    }
+  }
   Prof& P = prof();
   std::lock_guard<std::mutex> g(P.mu);
   P.on = true;
+  P.mask = mask;
   P.used = 0;
   P.cls.clear();
   return SHS_OK;
