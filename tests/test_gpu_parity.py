@@ -656,6 +656,32 @@ def test_zero_iterations_and_tolerance_stop():
     assert np.sqrt(st["r_combined"]) <= 1e-2 * np.sqrt(3 * 64 * 64)
 
 
+def test_profile_times_only_selected_classes():
+    # event timing of chosen kernel classes does not change results; only those classes report
+    pkg = _pkg()
+    w = make_small(64, 3, 2, seed=5, lam=0.1, iters=6)
+    plan = pkg.Plan(64, 1, 3, 2)
+    ws = plan.new_workspace()
+    s = torch.empty((3, 64, 64), device="cuda:0")
+    plan.datacost(dev_t(w.img), w.codebook, s)
+    u0 = torch.empty_like(s)
+    plan.solve(s, ws, w.lam, 1.0, 6, u=u0)
+    pkg.shs_profile_begin(["row_solve", "pixel"])
+    u1 = torch.empty_like(s)
+    plan.solve(s, ws, w.lam, 1.0, 6, u=u1)
+    torch.cuda.synchronize()
+    prof = pkg.shs_profile_end()
+    assert set(prof) == {"row_solve", "pixel"}
+    assert prof["row_solve"][0] >= 5 and prof["pixel"][0] >= 5
+    assert all(ms > 0 for _, ms in prof.values())
+    assert torch.equal(u0, u1)
+    pkg.shs_profile_begin()
+    plan.solve(s, ws, w.lam, 1.0, 6, u=u1)
+    torch.cuda.synchronize()
+    prof = pkg.shs_profile_end()
+    assert {"row_solve", "pixel", "col_syn", "col_ana"} <= set(prof)
+
+
 def test_energy_entry_point():
     pkg = _pkg()
     w = make_small(128, 3, 2, seed=8)
