@@ -977,16 +977,21 @@ shs_status shs_profile_begin_classes(const char* classes) {
   if (!classes || !*classes) {
     mask = ~0u;
   } else {
-    std::string list(classes);
-    size_t pos = 0;
-    while (pos <= list.size()) {
-      const size_t end = std::min(list.find(',', pos), list.size());
-      const std::string name = list.substr(pos, end - pos);
+    // comma-separated names, matched in place (no allocation)
+    const char* p = classes;
+    for (;;) {
+      const char* e = p;
+      while (*e && *e != ',') ++e;
+      const size_t len = size_t(e - p);
       int c = 0;
-      while (c < KC_COUNT && name != kKClassName[c]) ++c;
-      if (c == KC_COUNT) return fail(SHS_E_INVALID, "unknown kernel class '" + name + "'");
+      while (c < KC_COUNT && !(std::strlen(kKClassName[c]) == len && std::strncmp(kKClassName[c], p, len) == 0)) ++c;
+      if (c == KC_COUNT) {
+        g_err.assign("unknown kernel class '").append(p, len).append("'");
+        return SHS_E_INVALID;
+      }
       mask |= 1u << c;
-      pos = end + 1;
+      if (!*e) break;
+      p = e + 1;
     }
   }
   Prof& P = prof();
