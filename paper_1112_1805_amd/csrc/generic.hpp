@@ -85,10 +85,21 @@ __device__ __forceinline__ void gstage(const float2* __restrict__ src, float2* _
     cpx a[R];
     static_for<R>([&](auto i) { a[i] = ld(src + (int(bf) + i * nb) * W + c); });
     if (Ns > 1) {
+      // z^i with z = W_{Ns R}^k: the power-of-two exponents are loaded, the others are
+      // products of two of them (fewer loads through the vector-memory data path)
+      cpx w[R];
+      static_for<R>([&](auto i) {
+        if constexpr (i > 0 && (i & (i - 1)) == 0) w[i] = ld(sw + (i * Ns + k - 1));
+      });
+      static_for<R>([&](auto i) {
+        if constexpr (i > 0 && (i & (i - 1)) != 0) {
+          constexpr int hi = 1 << (31 - __builtin_clz(unsigned(i)));
+          w[i] = cmul(w[hi], w[i - hi]);
+        }
+      });
       static_for<R - 1>([&](auto i1) {
         constexpr int i = i1 + 1;
-        const cpx w = ld(sw + (i * Ns + k - 1));
-        a[i] = INV ? cmulc(a[i], w) : cmul(a[i], w);
+        a[i] = INV ? cmulc(a[i], w[i]) : cmul(a[i], w[i]);
       });
     }
     dft_any<R, INV>(a);
