@@ -402,9 +402,11 @@ __device__ __forceinline__ void row_c2r(cpx (&a)[RowGeom<N>::R], const float2* _
   const PlaneBuf B(X, pitch * N);
   const int ip0 = t - cb, im0 = G::M - t - cb;
   const int op0 = tix<N>(ip0, row), om0 = tix<N>(im0, row);
-  // Every bin outside the plane's columns maps below 0 or at or above pitch * N: its load
-  // is out of range and reads zero.  The loads are issued unconditionally (no per-chunk
-  // branch, no zero fill): they cost memory-pipe slots, which this VALU-bound pass has spare.
+  // Chunk r covers k in [r T, r T + T) for every row of the wave; whether it meets the
+  // window (directly or mirrored) is uniform, so chunks outside it are skipped whole.  Bins
+  // of a partly covered chunk outside the plane's columns map below 0 or at or above
+  // pitch * N: their loads are out of range and read zero.  (Issuing every load instead of
+  // branching was measured slower: the memory data path, not the VALU, is the tighter limit.)
   cpx xp[G::R], xm[G::R];
   static_for<G::R>([&](auto r) {
     constexpr int k0 = r * G::T;
