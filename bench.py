@@ -610,6 +610,16 @@ def main():
         row_solve_hbm = {"avg_launch_ms": round(rs[1] / rs[0], 5),
                          "achieved_GBs": round(b / (rs[1] / rs[0] / 1e3) / 1e9, 1),
                          "frac": round(b / (rs[1] / rs[0] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        # the same launch against the ALU: conventional FFT flops of its two real row FFTs
+        # (inverse and forward, 2.5 N log2 N each) per coefficient row; the binding limit of
+        # this kernel is instruction issue, not HBM
+        lg = (2 * w.n).bit_length() - 2
+        fl = eta * w.q * w.n * 2 * 2.5 * w.n * lg
+        tf = fl / (rs[1] / rs[0] / 1e3) / 1e12
+        row_solve_hbm["fft_flops_per_launch"] = fl
+        row_solve_hbm["fft_TFLOPs"] = round(tf, 2)
+        row_solve_hbm["fft_frac_of_157_3"] = round(tf / FP32_VALU_PEAK_TFS, 4)
+        row_solve_hbm["fft_frac_of_nonpacked_78_6"] = round(tf / (FP32_VALU_PEAK_TFS / 2), 4)
     # whole-iteration roofline: algorithmic bytes per iteration over the iteration time
     bytes_iter = 2.0 * store_bytes * eta * w.q * w.n * w.n + 12.0 * w.q * w.n * w.n
     iter_hbm_frac = bytes_iter * its / 1e9 / HBM_PEAK_GBS
