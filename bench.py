@@ -190,6 +190,7 @@ def run_batch(args):
         "ms_per_iter": round(dt / args.steps / iters * 1e3, 4),
         "setup_ms": round(setup_ms, 1),
         "workspace_gb": round(batch.workspace_bytes() / 1e9, 2),
+        "source_hash": source_hash(),
     }
     print(json.dumps(out), flush=True)
 
