@@ -210,8 +210,8 @@ constexpr int col_lds_points() { return L + L / R; }
 // The Q - 1 twiddles w[r] = z^r (1 <= r < Q, Q a power of two) of one butterfly: the
 // powers z^1, z^2, z^4, z^8 are loaded (entry (r-1)*stride of `p`), the others are
 // products of two of them (at most three roundings from the table values).  Loads go
-// through the vector-memory data path, which the row pass saturates; the products cost
-// a few FMAs each.
+// through the vector-memory data path, which the row pass keeps near saturation; the
+// products cost a few FMAs each.
 template <int Q>
 __device__ __forceinline__ void pow2_twiddles(const float2* __restrict__ p, int stride, cpx (&w)[Q]) {
   static_for<Q>([&](auto r) {

@@ -239,7 +239,8 @@ __global__ void k_datacost(const float* __restrict__ img, int C, Codebook cb, in
 // Column FFTs have complex length N: radix R (and middle radix RM), one strip of W
 // adjacent columns per block, W * T threads.  Strip s holds columns [s W, s W + W) (only
 // those <= N/2 exist).  Strips are stored as contiguous blocks, so W only trades block
-// size against occupancy (W = 4 at N = 1024: 256 threads, 32 KB LDS, 3 blocks per CU).
+// size against occupancy (W = 4 at N = 1024: 256 threads, 34 KB of LDS with the pad
+// slots, four blocks per CU).
 // WPE is the occupancy hint of the filtered column passes (waves per SIMD).  At N = 2048
 // they run at two waves and load the next filter's spectrum column and filter values
 // during the current FFT (PREFETCH); with more waves per SIMD those extra registers would
@@ -406,7 +407,8 @@ __device__ __forceinline__ void row_c2r(cpx (&a)[RowGeom<N>::R], const float2* _
   // window (directly or mirrored) is uniform, so chunks outside it are skipped whole.  Bins
   // of a partly covered chunk outside the plane's columns map below 0 or at or above
   // pitch * N: their loads are out of range and read zero.  (Issuing every load instead of
-  // branching was measured slower: the memory data path, not the VALU, is the tighter limit.)
+  // branching was measured slower: this pass keeps the vector-memory data path near
+  // saturation.)
   cpx xp[G::R], xm[G::R];
   static_for<G::R>([&](auto r) {
     constexpr int k0 = r * G::T;
