@@ -211,9 +211,10 @@ def make_c3(count: int = 64) -> list[Workload]:
     return [make_c3_image(i) for i in range(count)]
 
 
-def make_c4(index: int = 0, n: int = 2048) -> Workload:
+def make_c4(index: int = 0, n: int = 2048, q: int = 8) -> Workload:
+    """C4; `q` < 8 gives the same image class with q grey levels (a label count the
+    oracle can run at 2048^2 in host memory)."""
     rng = _rng(4, index)
-    q = 8
     levels = np.linspace(0.0, 1.0, q)
     lab = curved_voronoi_labels(n, q, 32, rng)
     textured = rng.uniform(size=q) < 0.5
