@@ -181,7 +181,7 @@ def run_batch(args):
         "metric": "batch ADMM iters/s (all images advance one iteration) and Mpixel·label·filter/s",
         "value": round(its, 3), "unit": "batch-iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(dt / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": f"f32 (state {store})", "data": "synthetic",
         "config": {"workload": f"C3: {len(ws_)} gray images, sides {ns[0]}..{ns[-1]} (32*m), q 2..6, J=3 (29 filters), "
                                f"{iters} ADMM iterations, {store} state, one captured graph per iteration",
                    "images": len(ws_), "iters_per_step": iters, "state_storage": store,
@@ -336,7 +336,7 @@ def run_pd(args):
         "metric": "primal-dual iters/s and Mpixel·label·filter/s at 1024^2 K=5 J=4",
         "value": round(its, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(dt / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": f"f32 (state {store})", "data": "synthetic",
         "config": {"workload": f"{describe(w, store, iters)}; solver: primal-dual (Chambolle-Pock), "
                                f"tau={tau}, sigma={sigma}", "iters_per_step": iters, "state_storage": store},
         "mpixel_label_filter_per_s": round(its * w.n * w.n * w.q * eta / 1e6, 1),
@@ -411,7 +411,7 @@ def run_tv(args):
         "metric": "TV-model ADMM iters/s at 1024^2 K=5 (comparison model of Section 4)",
         "value": round(its, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(dt / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": f"f32 (state {store})", "data": "synthetic",
         "config": {"workload": f"C2 data (1024x1024 RGB, q=5), TV weight {lam}, gamma {gamma}, {iters} iterations, "
                                f"{store} state", "iters_per_step": iters, "state_storage": store},
         "ms_per_iter": round(dt / args.steps / iters * 1e3, 4),
@@ -487,7 +487,7 @@ def run_nl(args):
         "metric": "NL-model primal-dual iters/s at 1024^2 K=5 (comparison model of Section 4)",
         "value": round(its, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(dt / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": f"f32 (state {store})", "data": "synthetic",
         "config": {"workload": f"C2 data (1024x1024 RGB, q=5), NL-means graph (patch 5, window 15, a=2, m=5), "
                                f"weight {lam}, tau=sigma={tau:.4f}, {iters} iterations, {store} dual variable",
                    "iters_per_step": iters, "state_storage": store, "max_degree": md},
@@ -637,7 +637,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": f"f32 (state {args.store})",
         "data": "synthetic",
         "config": {"workload": describe(w, args.store, iters), "image": f"{w.n}x{w.n}x{w.channels}",
                    "labels": w.q, "scales": w.J, "filters": eta, "iters_per_step": iters,
@@ -652,6 +652,14 @@ def main():
         "final_stats": {k: (round(v, 9) if isinstance(v, float) else v) for k, v in st.items()},
         "source_hash": khash,
     }
+
+    # the same solve without kernel timing: steady-state iterations replayed from captured
+    # graphs (with timing on, the library launches every kernel eagerly)
+    gr = run_gpu(args, w, args.store, iters, max(1, args.steps), 1, profile=None)
+    out["graph_path"] = {"iters_per_s": round(max(1, args.steps) * iters / gr["seconds"], 3),
+                         "ms_per_iter": round(gr["seconds"] / max(1, args.steps) / iters * 1e3, 4),
+                         "energy": gr["stats"]["energy"]}
+    del gr
 
     if not args.no_f32 and args.store != "f32":
         f32 = run_gpu(args, w, "f32", iters, 1, 1, profile=None)

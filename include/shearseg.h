@@ -57,7 +57,11 @@ typedef enum {
 } shs_status;
 
 /* Storage type of the dominant ADMM state (the eta*q coefficient images); arithmetic is
- * FP32 throughout, residual and energy reductions FP64. */
+ * FP32 throughout, residual and energy reductions FP64.  SHS_STORE_F16 holds |g| < 65504 for
+ * the stored g = b_v + S u; since |b_v| <= gamma lambda_j and the first iterate is
+ * u = -gamma s / 2, keep gamma * max(s) well below 1e4 (e.g. scale 8-bit images to [0, 1]).
+ * shs_solve on an F16 plan always checks the last iteration for non-finite values (one
+ * synchronisation) and returns SHS_E_NUMERIC if the state overflowed. */
 typedef enum { SHS_STORE_F32 = 0, SHS_STORE_BF16 = 1, SHS_STORE_F16 = 2 } shs_store;
 
 #define SHS_MAX_LABELS 8
@@ -66,7 +70,8 @@ typedef enum { SHS_STORE_F32 = 0, SHS_STORE_BF16 = 1, SHS_STORE_F16 = 2 } shs_st
 typedef struct shs_plan shs_plan;   /* opaque: filter bank, twiddles, sizes, device */
 
 typedef struct {
-  int32_t n;         /* image side N (square images, Section 2); 64..2048, power of two */
+  int32_t n;         /* image side N (square images, Section 2): a power of two in 64..2048, or a
+                        multiple of 8 in 64..1024 whose prime factors are all <= 23 (mixed radix) */
   int32_t channels;  /* 1 = gray, 3 = RGB (data term only); 1..SHS_MAX_CHANNELS */
   int32_t q;         /* number of labels, 1..SHS_MAX_LABELS */
   int32_t J;         /* number of shearlet scales, J >= 1 and 4^J <= 2N */
@@ -159,8 +164,14 @@ shs_status shs_shearlet_denoise(const shs_plan* plan, int32_t count, const float
  * be NULL).  d_hist: NULL or float64 [iters][4] = (r_primal, r_dual, r_combined,
  * energy_surrogate) per iteration.  h_stats: NULL (no synchronisation) or receives the final
  * statistics, including the exact energy (one extra forward transform of w^K).
+ * Launches: with tol = 0 and at least 10 iterations, the iterations between the first and
+ * the last few are replayed from a captured HIP graph of 8 iterations (captured on a stream
+ * of the plan's own at first use for a given workspace, data term, history buffer and
+ * parameters, and kept by the plan, a few per plan); while kernel timing is on
+ * (shs_profile_begin) every launch is eager.  Results are the same either way.
  * Errors: SHS_E_INVALID, SHS_E_WORKSPACE, SHS_E_DEVICE, SHS_E_NUMERIC (non-finite residual
- * at a checked iteration). */
+ * at a checked iteration; with SHS_STORE_F16 the last iteration is always checked, which
+ * synchronises the stream). */
 shs_status shs_solve(const shs_plan* plan, const shs_params* params, const float* d_s, void* d_ws,
                      size_t ws_bytes, float* d_u, int32_t* d_labels, double* d_hist, shs_stats* h_stats,
                      void* stream);
@@ -273,7 +284,8 @@ shs_status shs_energy(const shs_plan* plan, const shs_params* params, const floa
  * d_s, d_u, d_labels: HOST arrays of `count` device pointers (d_u / d_labels and their
  * entries may be NULL); layouts as in shs_solve.  d_stats: NULL or DEVICE float64
  * [count][5] receiving, per image, the last iteration's |dy|^2, |db|^2, <w,s>,
- * sum lambda|v| and a non-finite flag (1.0 if any of them is not finite).
+ * sum lambda|v| and a non-finite flag (1.0 if any of them is not finite); all zeros
+ * when iters = 0.
  * A batch object is not thread-safe (it owns its captured graphs). */
 typedef struct shs_batch shs_batch;
 shs_status shs_batch_create(int32_t count, const shs_shape* shapes, int device, shs_batch** out);

@@ -225,6 +225,15 @@ __device__ __forceinline__ void pow2_twiddles(const float2* __restrict__ p, int 
   });
 }
 
+// The same Q - 1 twiddles read directly, entry (r-1)*stride each: used when the table
+// sits in LDS, where a read costs no vector-memory bandwidth and no products are needed.
+template <int Q>
+__device__ __forceinline__ void all_twiddles(const float2* p, int stride, cpx (&w)[Q]) {
+  static_for<Q>([&](auto r) {
+    if constexpr (r > 0) w[r] = ld(p + (r - 1) * stride);
+  });
+}
+
 // Inter-stage twiddles of one FFT configuration, stored in the order the threads read
 // them so that the lanes of a wave load consecutive entries (a table indexed by the
 // exponent r*t would be read with stride r and touch up to one cache line per lane):
@@ -238,8 +247,9 @@ constexpr int stage_tw_size() { return (R - 1) * (L / R) + (RM - 1) * R; }
 // In-register/LDS Stockham FFT of length L.  On entry a[r] holds point t + r*T; on exit
 // a[r] holds output bin t + r*T.  `sw` is the stage twiddle table of (L, R, RM) above.
 // The caller must have synchronised any earlier reader of the LDS region before the call
-// (the routine synchronises before its first LDS write).
-template <int L, int R, int RM, bool INV, int SK, class Addr>
+// (the routine synchronises before its first LDS write).  TWL: `sw` points to a copy of
+// the table in LDS, and every twiddle power is read from it.
+template <int L, int R, int RM, bool INV, int SK, class Addr, bool TWL = false>
 __device__ __forceinline__ void fft_run(cpx (&a)[R], const Addr& lds, int t, const float2* __restrict__ sw) {
   static_assert(R * R * RM == L && R % RM == 0, "FFT configuration");
   constexpr int T = L / R;                 // = R * RM
@@ -260,7 +270,8 @@ __device__ __forceinline__ void fft_run(cpx (&a)[R], const Addr& lds, int t, con
     });
     fft_sync<SK>();
     cpx w[RM];
-    pow2_twiddles<RM>(sw + (R - 1) * T + tr, R, w);
+    if constexpr (TWL) all_twiddles<RM>(sw + (R - 1) * T + tr, R, w);
+    else pow2_twiddles<RM>(sw + (R - 1) * T + tr, R, w);
     static_for<U>([&](auto u) {
       cpx c[RM];
       static_for<RM>([&](auto r) {
@@ -276,7 +287,8 @@ __device__ __forceinline__ void fft_run(cpx (&a)[R], const Addr& lds, int t, con
   }
   // last stage: radix R, Ns = L/R, butterfly bf = t; input t + r*T = (tq + r*RM) * R + tr
   cpx wl[R];
-  pow2_twiddles<R>(sw + t, T, wl);
+  if constexpr (TWL) all_twiddles<R>(sw + t, T, wl);
+  else pow2_twiddles<R>(sw + t, T, wl);
   static_for<R>([&](auto r) {
     cpx v = ld(lds.template at<R>(tq + r * RM, tr));
     if constexpr (r > 0) {

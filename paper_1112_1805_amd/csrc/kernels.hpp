@@ -312,15 +312,26 @@ template <> struct RowFft<256>  { static constexpr int R = 16, RM = 1; };
 template <> struct RowFft<512>  { static constexpr int R = 16, RM = 2; };
 template <> struct RowFft<1024> { static constexpr int R = 16, RM = 4; };
 
+// The row FFT's twiddles sit in LDS, copied once per block: the real-FFT pre/post factors
+// W_N^k (k < M for N <= 512; for larger N only W_N^t, t < T, and the other factors are
+// W_N^t times a compile-time constant) followed by the stage table of fft_run.  Reading
+// every stage power from LDS needs no products and takes those loads off the vector-memory
+// data path, which the row pass keeps busy.  Sizes keep four waves per SIMD: four blocks
+// of four waves per CU up to N = 1024, two blocks of eight waves at N = 2048.
 template <int N> struct RowGeom {
   static constexpr int M = N / 2;
   static constexpr int R = RowFft<M>::R;
   static constexpr int RM = RowFft<M>::RM;
   static constexpr int T = M / R;
   static constexpr int RPW = 64 / T;          // rows per wave
-  static constexpr int WAVES = 4;
+  static constexpr int WAVES = N >= 2048 ? 8 : 4;
+  static constexpr int THREADS = 64 * WAVES;
   static constexpr int RPB = RPW * WAVES;     // rows per block
   static constexpr int LROW = M + M / R;      // LDS float2 per row (padded)
+  static constexpr bool PREFULL = N <= 512;   // all M pre/post factors in LDS
+  static constexpr int TW_PRE = PREFULL ? M : T;
+  static constexpr int TW_STAGE = stage_tw_size<M, R, RM>();
+  static constexpr int TW_LDS = TW_PRE + TW_STAGE;
 };
 
 // Twiddle tables of a power-of-two plan, one device array: [0, N) holds exp(-2 pi i m / N);
@@ -393,12 +404,20 @@ __device__ __forceinline__ int row_bin(int base_ip, int base_off, int r, int row
   }
 }
 
+// W_N^k for k = t + r*T from the row pass's LDS twiddle table.
+template <int N, int r>
+__device__ __forceinline__ cpx pre_twiddle(const float2* twl, int t) {
+  using G = RowGeom<N>;
+  if constexpr (G::PREFULL) return ld(twl + t + r * G::T);
+  else return twc<r * G::T, N, false>(ld(twl + t));
+}
+
 // Inverse real FFT of a half-spectrum row (unnormalised): X[0..M] -> x[0..N) with
 // point pair (2p, 2p+1) of p = t + r*T in a[r] = (x[2p], x[2p+1]).  The plane holds the
-// columns [cb, cb + pitch); other bins are zero.
+// columns [cb, cb + pitch); other bins are zero.  twl: the block's LDS twiddle table.
 template <int N, class Addr>
 __device__ __forceinline__ void row_c2r(cpx (&a)[RowGeom<N>::R], const float2* __restrict__ X, int row, int cb,
-                                        int pitch, const Addr& A, int t, const float2* __restrict__ tw) {
+                                        int pitch, const Addr& A, int t, const float2* twl) {
   using G = RowGeom<N>;
   const PlaneBuf B(X, pitch * N);
   const int ip0 = t - cb, im0 = G::M - t - cb;
@@ -417,30 +436,27 @@ __device__ __forceinline__ void row_c2r(cpx (&a)[RowGeom<N>::R], const float2* _
     if (k0 < cb + pitch && k0 + G::T > cb) xp[r] = B.load(row_bin<N, 1>(ip0, op0, r, row));
     if (k0 <= G::M - cb && k0 + G::T > G::M - cb - pitch) xm[r] = B.load(row_bin<N, -1>(im0, om0, r, row));
   });
-  // W_N^k for k = t + r T as W_N^t times the compile-time constant W_N^{r T}: one load
-  const cpx w0 = ld(tw + t);
   static_for<G::R>([&](auto r) {
     const cpx s = xp[r] + conj(xm[r]), d = xp[r] - conj(xm[r]);
-    const cpx w = conj(twc<r * G::T, N, false>(w0));   // W_N^{-k}
+    const cpx w = conj(pre_twiddle<N, r>(twl, t));   // W_N^{-k}
     a[r] = s + mul_i(cmul(d, w));
   });
-  fft_run<G::M, G::R, G::RM, true, SYNC_WAVE>(a, A, t, tw + row_sw_off<N>());
+  fft_run<G::M, G::R, G::RM, true, SYNC_WAVE, Addr, true>(a, A, t, twl + G::TW_PRE);
 }
 
 // Forward real FFT of a row held as pairs a[r] = (x[2p], x[2p+1]); writes the bins of
 // X[0..M] that fall in [cb, cb + pitch).
 template <int N, class Addr>
 __device__ __forceinline__ void row_r2c(cpx (&a)[RowGeom<N>::R], float2* __restrict__ X, int row, int cb, int pitch,
-                                        const Addr& A, int t, const float2* __restrict__ tw) {
+                                        const Addr& A, int t, const float2* twl) {
   using G = RowGeom<N>;
-  fft_run<G::M, G::R, G::RM, false, SYNC_WAVE>(a, A, t, tw + row_sw_off<N>());
+  fft_run<G::M, G::R, G::RM, false, SYNC_WAVE, Addr, true>(a, A, t, twl + G::TW_PRE);
   const int tq = int(unsigned(t) / G::R), tr = int(unsigned(t) % G::R);
   fft_sync<SYNC_WAVE>();
   static_for<G::R>([&](auto r) { st(A.template at<G::R>(tq + r * G::RM, tr), a[r]); });
   fft_sync<SYNC_WAVE>();
   const PlaneBuf B(X, pitch * N);
   const int ip0 = t - cb, op0 = tix<N>(ip0, row);
-  const cpx w0 = ld(tw + t);
   static_for<G::R>([&](auto r) {
     constexpr int k0 = r * G::T;
     if (k0 < cb + pitch && k0 + G::T > cb) {
@@ -448,7 +464,7 @@ __device__ __forceinline__ void row_r2c(cpx (&a)[RowGeom<N>::R], float2* __restr
       const cpx yk = a[r];
       const cpx ym = conj(ld(A(unsigned(G::M - k) & unsigned(G::M - 1))));
       const cpx s = yk + ym, d = yk - ym;
-      const cpx w = twc<r * G::T, N, false>(w0);   // W_N^{k}
+      const cpx w = pre_twiddle<N, r>(twl, t);   // W_N^{k}
       B.store(row_bin<N, 1>(ip0, op0, r, row), (s - mul_i(cmul(d, w))) * 0.5f);
     }
   });
@@ -456,11 +472,12 @@ __device__ __forceinline__ void row_r2c(cpx (&a)[RowGeom<N>::R], float2* __restr
 }
 
 template <int N, int MODE, int ST, bool STATS>
-__global__ __launch_bounds__(256) void k_row(RowParams p) {
+__global__ __launch_bounds__(RowGeom<N>::THREADS) void k_row(RowParams p) {
   using G = RowGeom<N>;
   using S = Store<ST>;
   __shared__ float2 lds[G::RPB * G::LROW];
-  __shared__ double red[4 * 4];
+  __shared__ float2 twl[G::TW_LDS];
+  __shared__ double red[G::WAVES * 4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane / G::T, t = lane % G::T;
   const int rowl = wave * G::RPW + sub;
@@ -478,6 +495,10 @@ __global__ __launch_bounds__(256) void k_row(RowParams p) {
     gp = reinterpret_cast<typename S::T*>(p.g) + (long long)ch * N * N + (long long)row * N;
     static_for<G::R>([&](auto r) { gv[r] = S::load_pair(gp + 2 * (t + r * G::T)); });
   }
+  // the block's twiddle table (pre/post factors, then the FFT stage table)
+  for (int e = threadIdx.x; e < G::TW_LDS; e += G::THREADS)
+    twl[e] = p.tw[e < G::TW_PRE ? e : row_sw_off<N>() + (e - G::TW_PRE)];
+  __syncthreads();
 
   if constexpr (MODE == ROW_SOLVE || MODE == ROW_C2R || MODE == ROW_ENERGY || MODE == ROW_SHRINK || MODE == ROW_PD) {
     int cb, pitch;
@@ -485,7 +506,7 @@ __global__ __launch_bounds__(256) void k_row(RowParams p) {
     const int f = ch % p.lin.nf;
     plane_geom(p.lin, f, cb, pitch, off);
     const float2* X = p.spec_in + (ch / p.lin.nf) * p.lin.ls + off;
-    row_c2r<N>(a, X, row, cb, pitch, A, t, p.tw);
+    row_c2r<N>(a, X, row, cb, pitch, A, t, twl);
   }
   if constexpr (MODE == ROW_C2R) {
     float* out = p.real_out + ch * p.real_cs + (long long)row * N;
@@ -573,7 +594,7 @@ __global__ __launch_bounds__(256) void k_row(RowParams p) {
       const int f = ch % p.lout.nf;
       plane_geom(p.lout, f, cb, pitch, off);
       float2* X = p.spec_out + (ch / p.lout.nf) * p.lout.ls + off;
-      row_r2c<N>(a, X, row, cb, pitch, A, t, p.tw);
+      row_r2c<N>(a, X, row, cb, pitch, A, t, twl);
     }
   }
   if constexpr (STATS) {
@@ -1019,9 +1040,11 @@ __global__ __launch_bounds__(256) void k_reduce1(const double* __restrict__ part
 }
 
 // Level 2: one block; writes totals[0..3], the history row (r_primal, r_dual, r_combined,
-// surrogate energy) and a non-finite flag in totals[4].
+// surrogate energy) and a non-finite flag in totals[4].  With hist_ctr the row is
+// hist_row + 4 * (*hist_ctr) and the counter advances by one, so one launch sequence (a
+// captured graph) serves every iteration of a solve.
 __global__ __launch_bounds__(256) void k_reduce2(const double* __restrict__ in, int n, double* __restrict__ totals,
-                                                 double* __restrict__ hist_row, double gamma) {
+                                                 double* __restrict__ hist_row, double gamma, int* hist_ctr) {
   __shared__ double red[4 * 4];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int r = threadIdx.x; r < n; r += 256) {
@@ -1034,6 +1057,7 @@ __global__ __launch_bounds__(256) void k_reduce2(const double* __restrict__ in, 
     totals[0] = acc[0]; totals[1] = acc[1]; totals[2] = acc[2]; totals[3] = acc[3];
     const double comb = dy2 + db2;
     totals[4] = (isfinite(comb) && isfinite(acc[2]) && isfinite(acc[3])) ? 0.0 : 1.0;
+    if (hist_row && hist_ctr) hist_row += 4LL * (*hist_ctr)++;
     if (hist_row) {
       hist_row[0] = sqrt(db2);
       hist_row[1] = sqrt(dy2) / gamma;

@@ -41,6 +41,27 @@ struct shs_plan {
   int2* strips_ana;    // per strip {first analysis item, items}
   int n_syn, n_ana, n_part;
   long long nnz;       // stored filter values
+  struct GraphCache* graphs;  // captured steady-state iterations of shs_solve
+};
+
+// Executable graphs of steady-state ADMM iterations, keyed by everything the captured
+// launches bake in (workspace, data term, history, thresholds, iteration count).  Captured
+// on a stream of the plan's own and launched on the caller's stream; a few entries, least
+// recently used dropped first.  The mutex makes lookups, captures and launches of one plan
+// safe from several host threads.
+struct GraphCache {
+  struct Entry {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec;
+  };
+  std::mutex mu;
+  hipStream_t cap = nullptr;
+  std::vector<Entry> entries;   // most recently used last
+  static constexpr size_t kMax = 6;
+  ~GraphCache() {
+    for (Entry& e : entries) (void)hipGraphExecDestroy(e.exec);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
 };
 
 namespace {
@@ -102,6 +123,11 @@ struct Prof {
 Prof& prof() {
   static Prof p;
   return p;
+}
+bool profiling_on() {
+  Prof& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  return P.on;
 }
 // Set while a batch graph is being captured: no timing events inside graphs.
 thread_local int g_capturing = 0;
@@ -198,7 +224,7 @@ constexpr int kDotBlocks = 1024;
 
 struct Layout {
   size_t g, w, bw, state_end;
-  size_t t1, t2, v, z, zs, us, part, parts, red1, sdev, total;
+  size_t t1, t2, v, z, zs, us, part, parts, red1, sdev, hctr, total;
   long long nrow_parts, nparts;
 };
 
@@ -223,7 +249,8 @@ Layout make_layout(const shs_plan* p) {
   L.nparts = L.nrow_parts + std::max<long long>(2 * npix, kDotBlocks);
   L.parts = off; off = align256(off + size_t(L.nparts) * 4 * 8);
   L.red1 = off;  off = align256(off + kRed1Blocks * 4 * 8);
-  L.sdev = off;  off = align256(off + 8 * 8);
+  L.sdev = off;  off = align256(off + 8 * 8);   // totals [0, 5), history row counter at [6]
+  L.hctr = L.sdev + 6 * 8;
   L.total = off;
   return L;
 }
@@ -237,7 +264,7 @@ struct Pipe {
   template <int MODE, int ST, bool STATS>
   static void row_t(const RowParams& rp, int channels, hipStream_t s) {
     dim3 grid(N / RG::RPB, channels);
-    hipLaunchKernelGGL((k_row<N, MODE, ST, STATS>), grid, dim3(256), 0, s, rp);
+    hipLaunchKernelGGL((k_row<N, MODE, ST, STATS>), grid, dim3(RG::THREADS), 0, s, rp);
   }
   static void row(const shs_plan*, int mode, int store, bool stats, const RowParams& rp, int channels, hipStream_t s) {
     switch (mode) {
@@ -514,20 +541,22 @@ void enqueue_analysis(const Ctx& c, int count) {
   if (p->n_part > 0) run_col(c, COL_FINAL, cp, p->NS, count);
 }
 
-void enqueue_reduce(const Ctx& c, long long nparts, double* hist_row, double gamma) {
+// hist_ctr: NULL (hist_row is the row itself) or the device row counter (hist_row is the
+// history's first row).
+void enqueue_reduce(const Ctx& c, long long nparts, double* hist_row, double gamma, int* hist_ctr = nullptr) {
   Timed tm(c.s, KC_REDUCE);
   const long long per = (nparts + kRed1Blocks - 1) / kRed1Blocks;
   hipLaunchKernelGGL(k_reduce1, dim3(kRed1Blocks), dim3(256), 0, c.s, c.at<double>(c.L.parts), nparts,
                      std::max<long long>(per, 1), c.at<double>(c.L.red1));
   hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(256), 0, c.s, c.at<double>(c.L.red1), kRed1Blocks,
-                     c.at<double>(c.L.sdev), hist_row, gamma);
+                     c.at<double>(c.L.sdev), hist_row, gamma, hist_ctr);
 }
 
 // Per-filter weights and thresholds from a host Lambda (J+1 per-scale or eta per-filter).
 shs_status set_lambda(Ctx& c, const shs_params* prm) {
   const int eta = c.p->eta, J = c.p->J;
   if (!prm->lambda) return fail(SHS_E_INVALID, "null lambda");
-  std::vector<float> lam_f(eta, 0.f);
+  float lam_f[kMaxFilters] = {};   // eta <= kMaxFilters (J <= 6); no heap allocation
   if (prm->lambda_len == eta) {
     for (int f = 0; f < eta; ++f) lam_f[f] = prm->lambda[f];
   } else if (prm->lambda_len == J + 1) {
@@ -538,8 +567,9 @@ shs_status set_lambda(Ctx& c, const shs_params* prm) {
   } else {
     return fail(SHS_E_INVALID, "lambda_len must be J+1 or eta");
   }
-  for (float v : lam_f)
-    if (!(v >= 0.f) || !std::isfinite(v)) return fail(SHS_E_INVALID, "lambda entries must be finite and >= 0");
+  for (int f = 0; f < eta; ++f)
+    if (!(lam_f[f] >= 0.f) || !std::isfinite(lam_f[f]))
+      return fail(SHS_E_INVALID, "lambda entries must be finite and >= 0");
   std::memset(&c.fw, 0, sizeof(c.fw));
   for (int f = 0; f < eta; ++f) {
     c.fw.lam[f] = lam_f[f];
@@ -576,6 +606,7 @@ shs_status energy_of(const Ctx& c, const float* d_u, const float* d_s, double* o
 // ---------------------------------------------------------------- plan construction
 void free_plan(shs_plan* p) {
   if (!p) return;
+  delete p->graphs;
   void* bufs[] = {p->psi, p->tw, p->eig, p->psiw, p->pwin, p->tcol, p->items_syn, p->items_ana, p->flist,
                   p->strips_ana};
   for (void* b : bufs)
@@ -707,7 +738,7 @@ void enqueue_epilogue(const Ctx& c, float* d_u, int32_t* d_labels) {
 // v/b_v update fused with the next adjoint's row FFT (when `emit`), optional FP64 residual
 // reduction into `hist_row`.  Enqueues only; no host synchronisation.
 void enqueue_iteration(const Ctx& c, const float* d_s, float gamma, bool have_adjoint_input, bool stats, bool emit,
-                       double* hist_row) {
+                       double* hist_row, int* hist_ctr = nullptr) {
   const shs_plan* p = c.p;
   const Layout& L = c.L;
   const int q = p->q;
@@ -751,7 +782,7 @@ void enqueue_iteration(const Ctx& c, const float* d_s, float gamma, bool have_ad
   rp.g = c.ws + L.g;
   rp.emit = emit ? 1 : 0;
   run_row(c, ROW_SOLVE, p->store, stats, rp, q * p->eta);
-  if (stats) enqueue_reduce(c, L.nrow_parts + npix_blocks, hist_row, gamma);
+  if (stats) enqueue_reduce(c, L.nrow_parts + npix_blocks, hist_row, gamma, hist_ctr);
 }
 
 template <int ST>
@@ -952,6 +983,71 @@ struct shs_batch {
 namespace {
 }  // namespace
 
+// ---------------------------------------------------------------- graph replay
+constexpr int kGraphIters = 8;   // ADMM iterations per captured graph
+
+namespace {
+// Enqueues `reps` x `k` steady-state ADMM iterations (adjoint input present, next adjoint
+// input emitted, statistics only when a history is kept) on c.s by replaying a captured
+// graph of k iterations.  The graph is captured on first use for this key.
+shs_status replay_iterations(const Ctx& c, const float* d_s, float gamma, double* d_hist, int* hctr, int k, int reps) {
+  const shs_plan* p = c.p;
+  GraphCache& G = *p->graphs;
+  std::vector<uint64_t> key;
+  key.reserve(8 + 2 * kMaxFilters);
+  auto put = [&](const void* ptr) { key.push_back(uint64_t(reinterpret_cast<uintptr_t>(ptr))); };
+  put(c.ws); put(d_s); put(d_hist); put(hctr);
+  key.push_back(uint64_t(k));
+  uint32_t gb;
+  std::memcpy(&gb, &gamma, 4);
+  key.push_back(gb);
+  for (int f = 0; f < p->eta; ++f) {
+    uint32_t a, b;
+    std::memcpy(&a, &c.fw.thr[f], 4);
+    std::memcpy(&b, &c.fw.lam[f], 4);
+    key.push_back((uint64_t(a) << 32) | b);
+  }
+  std::lock_guard<std::mutex> lock(G.mu);
+  hipGraphExec_t exec = nullptr;
+  for (size_t i = 0; i < G.entries.size(); ++i) {
+    if (G.entries[i].key == key) {
+      GraphCache::Entry e = G.entries[i];
+      G.entries.erase(G.entries.begin() + long(i));
+      G.entries.push_back(e);
+      exec = e.exec;
+      break;
+    }
+  }
+  if (!exec) {
+    if (!G.cap) HIPCHK(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+    Ctx cc = c;
+    cc.s = G.cap;
+    {
+      CaptureScope cs;
+      HIPCHK(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
+      for (int i = 0; i < k; ++i) enqueue_iteration(cc, d_s, gamma, true, d_hist != nullptr, true, d_hist, hctr);
+      const hipError_t el = hipGetLastError();
+      hipGraph_t g = nullptr;
+      const hipError_t ee = hipStreamEndCapture(G.cap, &g);
+      if (el != hipSuccess || ee != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(SHS_E_DEVICE, "capture of the iteration graph failed");
+      }
+      const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) return fail(SHS_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    }
+    if (G.entries.size() >= GraphCache::kMax) {
+      (void)hipGraphExecDestroy(G.entries.front().exec);
+      G.entries.erase(G.entries.begin());
+    }
+    G.entries.push_back(GraphCache::Entry{key, exec});
+  }
+  for (int r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(exec, c.s));
+  return SHS_OK;
+}
+}  // namespace
+
 // ===================================================================== C ABI
 extern "C" {
 
@@ -1061,6 +1157,8 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
 
   shs_plan* p = new (std::nothrow) shs_plan{};
   if (!p) return fail(SHS_E_NOMEM, "host allocation");
+  p->graphs = new (std::nothrow) GraphCache();
+  if (!p->graphs) { delete p; return fail(SHS_E_NOMEM, "host allocation"); }
   p->n = n; p->C = shape->channels; p->q = shape->q; p->J = shape->J; p->store = shape->store;
   p->eta = shs_num_filters(shape->J);
   p->M = n / 2;
@@ -1506,8 +1604,14 @@ shs_status shs_energy(const shs_plan* p, const shs_params* prm, const float* d_s
   return energy_of(c, d_u, d_s, h_energy);
 }
 
-shs_status shs_solve(const shs_plan* p, const shs_params* prm, const float* d_s, void* d_ws, size_t ws_bytes,
-                     float* d_u, int32_t* d_labels, double* d_hist, shs_stats* h_stats, void* stream) {
+}  // extern "C"
+
+namespace {
+// shs_solve; allow_graphs = false keeps every launch eager (no graph capture or
+// instantiation, which may allocate).
+shs_status solve_impl(const shs_plan* p, const shs_params* prm, const float* d_s, void* d_ws, size_t ws_bytes,
+                      float* d_u, int32_t* d_labels, double* d_hist, shs_stats* h_stats, void* stream,
+                      bool allow_graphs) {
   if (!p || !prm || !d_s) return fail(SHS_E_INVALID, "null argument");
   shs_status st = check_params(prm);
   if (st != SHS_OK) return st;
@@ -1536,15 +1640,35 @@ shs_status shs_solve(const shs_plan* p, const shs_params* prm, const float* d_s,
   bool have_adjoint_input = prm->resume != 0;
   double last_tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   bool have_last = false;
+  // History rows are addressed through a device counter (reset here), so the launches of
+  // every steady-state iteration are identical.
+  int* hctr = d_hist ? c.at<int>(c.L.hctr) : nullptr;
+  if (hctr) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, c.s, reinterpret_cast<uint32_t*>(hctr), 1LL, 0u);
+  // FP16 state overflows to inf beyond 65504: the last iteration's non-finite flag is
+  // always reduced and checked for it (one synchronisation), also without h_stats.
+  const bool f16_guard = p->store == SHS_STORE_F16;
+  // Steady-state iterations (not the first, not the last; no host check in between) are
+  // replayed from captured graphs of kGraphIters iterations unless kernel timing is on.
+  const bool graphs = allow_graphs && prm->tol == 0.0 && prm->iters >= 4 && !profiling_on();
   for (int it = 0; it < prm->iters; ++it) {
     const bool last = it == prm->iters - 1;
+    if (graphs && it >= 1 && it + kGraphIters < prm->iters) {
+      const int reps = (prm->iters - 1 - it) / kGraphIters;
+      st = replay_iterations(c, d_s, prm->gamma, d_hist, hctr, kGraphIters, reps);
+      if (st != SHS_OK) return st;
+      it += reps * kGraphIters - 1;
+      have_adjoint_input = true;
+      done = it + 1;
+      continue;
+    }
     const bool check = prm->tol > 0.0 && ((it + 1) % prm->check_every == 0 || last);
-    const bool stats = d_hist != nullptr || check || (last && h_stats != nullptr);
-    enqueue_iteration(c, d_s, prm->gamma, have_adjoint_input, stats, !last, d_hist ? d_hist + 4LL * it : nullptr);
+    const bool want_last = last && (h_stats != nullptr || f16_guard);
+    const bool stats = d_hist != nullptr || check || want_last;
+    enqueue_iteration(c, d_s, prm->gamma, have_adjoint_input, stats, !last, d_hist, hctr);
     LAUNCHCHK("iteration");
     have_adjoint_input = true;
     done = it + 1;
-    if (check || (last && h_stats)) {
+    if (check || want_last) {
       HIPCHK(hipMemcpyAsync(last_tot, c.at<double>(c.L.sdev), 5 * 8, hipMemcpyDeviceToHost, c.s));
       HIPCHK(hipStreamSynchronize(c.s));
       have_last = true;
@@ -1570,6 +1694,15 @@ shs_status shs_solve(const shs_plan* p, const shs_params* prm, const float* d_s,
     *h_stats = out;
   }
   return SHS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+shs_status shs_solve(const shs_plan* p, const shs_params* prm, const float* d_s, void* d_ws, size_t ws_bytes,
+                     float* d_u, int32_t* d_labels, double* d_hist, shs_stats* h_stats, void* stream) {
+  return solve_impl(p, prm, d_s, d_ws, ws_bytes, d_u, d_labels, d_hist, h_stats, stream, true);
 }
 
 shs_status shs_batch_create(int32_t count, const shs_shape* shapes, int device, shs_batch** out) {
@@ -1694,10 +1827,14 @@ shs_status shs_solve_batch(shs_batch* b, const shs_params* params, const float* 
   }
   if (key != b->key) {
     b->drop_graphs();
-    auto tail = [&](int i) {   // epilogue + statistics of image i
+    auto tail = [&](int i) {   // epilogue + statistics of image i (zeros when no iteration ran)
       const Ctx& c = ctx[i];
       enqueue_epilogue(c, d_u ? d_u[i] : nullptr, d_labels ? d_labels[i] : nullptr);
-      if (d_stats) hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(64), 0, c.s, c.at<double>(c.L.sdev), 5, d_stats + 5LL * i);
+      if (d_stats && iters > 0)
+        hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(64), 0, c.s, c.at<double>(c.L.sdev), 5, d_stats + 5LL * i);
+      else if (d_stats)
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, c.s, reinterpret_cast<uint32_t*>(d_stats + 5LL * i),
+                           10LL, 0u);
     };
     shs_status st = SHS_OK;
     if (st == SHS_OK) st = b->capture([&] { for (int i : b->order) enqueue_zero_state(ctx[i]); }, &b->g_init);
