@@ -176,6 +176,21 @@ shs_status shs_solve(const shs_plan* plan, const shs_params* params, const float
                      size_t ws_bytes, float* d_u, int32_t* d_labels, double* d_hist, shs_stats* h_stats,
                      void* stream);
 
+/* Allocation-free variant of shs_solve, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments and results as shs_solve except the workspace: the library keeps one
+ * device array of SHS_NOALLOC_MAX_BYTES per GPU for the life of the process and uses it
+ * in place of d_ws; the call itself allocates nothing (no hipMalloc / hipFree, and no graph
+ * capture: every launch is eager).  Plans
+ * whose shs_workspace_bytes() exceeds SHS_NOALLOC_MAX_BYTES are rejected with
+ * SHS_E_WORKSPACE (at 64 MiB: e.g. 128^2 with q = 3, J = 2 fits; 512^2 with q = 4, J = 3
+ * does not).  All calls on one GPU share that array and it keeps the last call's contents
+ * (params->resume = 1 continues from the state the previous call on this GPU left there):
+ * calls that overlap on one GPU race, so serialise them (one stream, or host-side order). */
+#define SHS_NOALLOC_MAX_BYTES (64ull << 20)
+shs_status shs_solve_noalloc(const shs_plan* plan, const shs_params* params, const float* d_s, float* d_u,
+                             int32_t* d_labels, double* d_hist, shs_stats* h_stats, void* stream);
+
 /* Parameters of the primal-dual solver.  lambda/lambda_len as in shs_params (the weights
  * of the regulariser, low-pass first); tau (primal) and sigma (dual) step sizes, finite,
  * > 0, tau * sigma <= 1 (the operator I_q (x) S has norm 1 by Theorem 2.2). */

@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("SHEARSEG_LIB") or os.path.join(_HERE, "libshearseg.so
 SHS_OK, SHS_E_INVALID, SHS_E_UNSUPPORTED, SHS_E_NOMEM, SHS_E_DEVICE, SHS_E_NUMERIC, SHS_E_WORKSPACE = \
     0, -1, -2, -3, -4, -5, -6
 SHS_STORE_F32, SHS_STORE_BF16, SHS_STORE_F16 = 0, 1, 2
+SHS_NOALLOC_MAX_BYTES = 64 << 20   # include/shearseg.h
 STORE_CODES = {"f32": SHS_STORE_F32, "bf16": SHS_STORE_BF16, "f16": SHS_STORE_F16}
 
 
@@ -82,6 +83,8 @@ _SIGS = {
     "shs_shearlet_denoise": (_I32, [_VP, _I32, ctypes.POINTER(ctypes.c_float), _I32, _VP, _VP, _VP, _SZ, _VP]),
     "shs_solve": (_I32, [_VP, ctypes.POINTER(ShsParams), _VP, _VP, _SZ, _VP, _VP, _VP,
                          ctypes.POINTER(ShsStats), _VP]),
+    "shs_solve_noalloc": (_I32, [_VP, ctypes.POINTER(ShsParams), _VP, _VP, _VP, _VP,
+                                 ctypes.POINTER(ShsStats), _VP]),
     "shs_solve_pd": (_I32, [_VP, ctypes.POINTER(ShsPdParams), _VP, _VP, _SZ, _VP, _VP, _VP,
                             ctypes.POINTER(ShsStats), _VP]),
     "shs_solve_tv": (_I32, [_VP, ctypes.POINTER(ShsParams), _VP, _VP, _SZ, _VP, _VP, _VP,
@@ -289,6 +292,24 @@ class Plan:
         _check(lib().shs_solve(self.handle, ctypes.byref(prm), _ptr(s), _ptr(ws), ws.numel(), _ptr(u),
                                _ptr(labels), _ptr(hist), ctypes.byref(st) if want_stats else None,
                                _stream(stream)), "shs_solve")
+        del keep
+        return st.as_dict() if want_stats else None
+
+    def solve_noalloc(self, s, lam, gamma, iters, u=None, labels=None, hist=None, want_stats=True,
+                      tol=0.0, check_every=1, resume=False, stream=None):
+        """shs_solve_noalloc: solve() with the library's per-GPU device array as workspace."""
+        _expect(s, (self.q, self.n, self.n), "f32", "d_s")
+        if u is not None:
+            _expect(u, (self.q, self.n, self.n), "f32", "d_u")
+        if labels is not None:
+            _expect(labels, (self.n, self.n), "i32", "d_labels")
+        if hist is not None:
+            _expect(hist, (iters, 4), "f64", "d_hist")
+        prm, keep = _params(lam, gamma, iters, tol, check_every, resume)
+        st = ShsStats()
+        _check(lib().shs_solve_noalloc(self.handle, ctypes.byref(prm), _ptr(s), _ptr(u), _ptr(labels), _ptr(hist),
+                                       ctypes.byref(st) if want_stats else None, _stream(stream)),
+               "shs_solve_noalloc")
         del keep
         return st.as_dict() if want_stats else None
 

@@ -1048,6 +1048,34 @@ shs_status replay_iterations(const Ctx& c, const float* d_s, float gamma, double
 }
 }  // namespace
 
+// ---------------------------------------------------------------- allocation-free solve
+// Workspace of shs_solve_noalloc: one file-scope device array per GPU, held until the
+// process ends.  Host code never passes `scratch` itself (on the host it is only a stand-in
+// for the symbol); it uses the device address that hipGetSymbolAddress returns for the
+// current device, looked up once per device on the first call there.
+static __device__ __align__(256) unsigned char scratch[SHS_NOALLOC_MAX_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current).
+shs_status scratch_address(int device, void** out) {
+  if (device < 0 || device >= kScratchDevices) return fail(SHS_E_UNSUPPORTED, "device ordinal too large");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(SHS_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return SHS_OK;
+}
+}  // namespace
+
 // ===================================================================== C ABI
 extern "C" {
 
@@ -1703,6 +1731,21 @@ extern "C" {
 shs_status shs_solve(const shs_plan* p, const shs_params* prm, const float* d_s, void* d_ws, size_t ws_bytes,
                      float* d_u, int32_t* d_labels, double* d_hist, shs_stats* h_stats, void* stream) {
   return solve_impl(p, prm, d_s, d_ws, ws_bytes, d_u, d_labels, d_hist, h_stats, stream, true);
+}
+
+shs_status shs_solve_noalloc(const shs_plan* p, const shs_params* prm, const float* d_s, float* d_u,
+                             int32_t* d_labels, double* d_hist, shs_stats* h_stats, void* stream) {
+  if (!p || !prm || !d_s) return fail(SHS_E_INVALID, "null argument");
+  const size_t need = shs_workspace_bytes(p);
+  if (need > SHS_NOALLOC_MAX_BYTES)
+    return fail(SHS_E_WORKSPACE, "this plan needs " + std::to_string(need) + " bytes of workspace; the "
+                "allocation-free solve holds at most " + std::to_string((unsigned long long)SHS_NOALLOC_MAX_BYTES));
+  DeviceGuard dg(p->device);
+  if (!dg.ok) return fail(SHS_E_DEVICE, "hipSetDevice failed");
+  void* ws = nullptr;
+  const shs_status st = scratch_address(p->device, &ws);
+  if (st != SHS_OK) return st;
+  return solve_impl(p, prm, d_s, ws, need, d_u, d_labels, d_hist, h_stats, stream, false);
 }
 
 shs_status shs_batch_create(int32_t count, const shs_shape* shapes, int device, shs_batch** out) {

@@ -26,8 +26,16 @@ def test_header_declares_expected_entry_points():
                  "shs_num_filters", "shs_filters", "shs_datacost", "shs_shearlet_forward",
                  "shs_shearlet_adjoint", "shs_shearlet_denoise", "shs_solve", "shs_solve_pd", "shs_solve_tv", "shs_nl_graph", "shs_solve_nl", "shs_energy", "shs_status_str", "shs_last_error",
                  "shs_batch_create", "shs_batch_destroy", "shs_batch_workspace_bytes", "shs_solve_batch",
-                 "shs_profile_begin", "shs_profile_begin_classes", "shs_profile_end"]:
+                 "shs_profile_begin", "shs_profile_begin_classes", "shs_profile_end", "shs_solve_noalloc"]:
         assert name in syms
+
+
+def test_noalloc_limit_matches_header():
+    m = re.search(r"#define\s+SHS_NOALLOC_MAX_BYTES\s+\((\d+)ull\s*<<\s*(\d+)\)", open(HEADER).read())
+    assert m and int(m.group(1)) << int(m.group(2)) == pkg.SHS_NOALLOC_MAX_BYTES
+    # argument checks happen before any device call
+    L = pkg.lib()
+    assert L.shs_solve_noalloc(None, None, None, None, None, None, None, None) == pkg.SHS_E_INVALID
 
 
 def test_library_exports_every_declared_symbol():
