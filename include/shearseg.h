@@ -291,10 +291,13 @@ shs_status shs_energy(const shs_plan* plan, const shs_params* params, const floa
  * (shs_batch_workspace_bytes).
  *
  * shs_solve_batch runs params[i] on image i from the zero state (tol and resume are not
- * supported: SHS_E_UNSUPPORTED; every image runs the same number of iterations).  The work
- * of one ADMM iteration of all images is captured once into a HIP graph (images spread over
- * internal streams so that small images run side by side) and the graphs are replayed on
- * `stream`: one graph launch per iteration.  Graphs are re-captured whenever a pointer or
+ * supported: SHS_E_UNSUPPORTED; every image runs the same number of iterations).  Each step
+ * of an ADMM iteration is one grouped launch per kernel configuration covering all images
+ * that use it (the blocks of every image's grid laid end to end, each block running exactly
+ * the single-image kernel's code), and the whole solve (zero start, all iterations,
+ * epilogue, statistics) is captured once into one HIP graph, replayed on `stream` with a
+ * single graph launch.  Results equal separate shs_solve calls bit for bit.  The graph and
+ * its task tables (device memory owned by the batch) are rebuilt whenever a pointer or
  * parameter differs from the previous call.  The call returns without synchronising.
  * d_s, d_u, d_labels: HOST arrays of `count` device pointers (d_u / d_labels and their
  * entries may be NULL); layouts as in shs_solve.  d_stats: NULL or DEVICE float64
@@ -303,6 +306,7 @@ shs_status shs_energy(const shs_plan* plan, const shs_params* params, const floa
  * when iters = 0.
  * A batch object is not thread-safe (it owns its captured graphs). */
 typedef struct shs_batch shs_batch;
+/* count: 1..65535 images. */
 shs_status shs_batch_create(int32_t count, const shs_shape* shapes, int device, shs_batch** out);
 shs_status shs_batch_destroy(shs_batch* batch);
 size_t shs_batch_workspace_bytes(const shs_batch* batch);

@@ -110,7 +110,7 @@ __device__ __forceinline__ void gstage(const float2* __restrict__ src, float2* _
 
 // Full transform: data in b0 (natural order) -> result (natural order) in the returned buffer.
 template <bool INV, int SK, int W>
-__device__ float2* gfft(float2* b0, float2* b1, const FftPlan& pl, int nthr, int tid, const float2* __restrict__ sw) {
+__device__ __forceinline__ float2* gfft(float2* b0, float2* b1, const FftPlan& pl, int nthr, int tid, const float2* __restrict__ sw) {
   float2* src = b0;
   float2* dst = b1;
   int Ns = 1;
@@ -167,15 +167,15 @@ __device__ __forceinline__ int tix_g(int ip, int row, int n) {
 }
 
 template <int MODE, int ST, bool STATS, int RW>
-__global__ __launch_bounds__(256) void k_row_g(RowParams p, GenParams gp) {
+__device__ __forceinline__ void row_g_body(const RowParams& p, const GenParams& gp, BlockId bid) {
   static_assert(kGW == 4, "tix_g assumes strips of 4 columns");
   using S = Store<ST>;
   extern __shared__ float2 gsm[];
   __shared__ double red[4 * 4];
   const int n = gp.n, M = n / 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int row0 = (blockIdx.x * 4 + wave) * RW;
-  const int ch = blockIdx.y;
+  const int row0 = (bid.x * 4 + wave) * RW;
+  const int ch = bid.y;
   const int j = ch % p.eta;
   float2* b0 = gsm + wave * 2 * M * RW;
   float2* b1 = b0 + M * RW;
@@ -303,10 +303,15 @@ __global__ __launch_bounds__(256) void k_row_g(RowParams p, GenParams gp) {
     dd[SLOT_L1] *= double(p.fw.lam[j]);
     block_sum4<4>(dd, red);
     if (threadIdx.x == 0) {
-      double* o = p.partials + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * 4;
+      double* o = p.partials + ((long long)bid.y * bid.gx + bid.x) * 4;
       o[0] = dd[0]; o[1] = dd[1]; o[2] = dd[2]; o[3] = dd[3];
     }
   }
+}
+
+template <int MODE, int ST, bool STATS, int RW>
+__global__ __launch_bounds__(256) void k_row_g(RowParams p, GenParams gp) {
+  row_g_body<MODE, ST, STATS, RW>(p, gp, own_block());
 }
 
 // ---------------------------------------------------------------- generic column passes
@@ -329,29 +334,33 @@ __device__ __forceinline__ void stage_item_g(const ColParams& p, int4 it, int M,
   }
 }
 
-__global__ __launch_bounds__(256) void k_colg_fwd(ColParams p, GenParams gp) {
+__device__ __forceinline__ void colg_fwd_body(const ColParams& p, const GenParams& gp, BlockId bid) {
   extern __shared__ float2 gsm[];
   const int n = gp.n, E = n * kGW;
   float2* b0 = gsm;
   float2* b1 = gsm + E;
-  const long long strip = blockIdx.y * (long long)n * p.P + (long long)blockIdx.x * E;
+  const long long strip = bid.y * (long long)n * p.P + (long long)bid.x * E;
   for (int e = threadIdx.x; e < E; e += 256) b0[e] = p.in[strip + e];
   __syncthreads();
   float2* r = gfft<false, SYNC_BLOCK, kGW>(b0, b1, gp.pcol, 256, threadIdx.x, col_sw_g(p.tw, gp.n));
   const int M = n / 2;
   for (int e = threadIdx.x; e < E; e += 256)
-    if (blockIdx.x * kGW + (e % kGW) <= M) p.out[strip + e] = r[e];
+    if (bid.x * kGW + (e % kGW) <= M) p.out[strip + e] = r[e];
 }
 
-__global__ __launch_bounds__(256) void k_colg_syn(ColParams p, GenParams gp) {
+__global__ __launch_bounds__(256) void k_colg_fwd(ColParams p, GenParams gp) {
+  colg_fwd_body(p, gp, own_block());
+}
+
+__device__ __forceinline__ void colg_syn_body(const ColParams& p, const GenParams& gp, BlockId bid) {
   extern __shared__ float2 gsm[];
   const int n = gp.n, E = n * kGW, M = n / 2;
   float2* bu = gsm;
   float2* b0 = gsm + E;
   float2* b1 = gsm + 2 * E;
   __shared__ ItemStage<kGW> stg;
-  const int4 it = p.items[blockIdx.x];
-  const int l = blockIdx.y;
+  const int4 it = p.items[bid.x];
+  const int l = bid.y;
   stage_item_g(p, it, M, stg);
   const float2* U = p.in + l * (long long)n * p.P + (long long)it.x * E;
   for (int e = threadIdx.x; e < E; e += 256) bu[e] = U[e];
@@ -371,7 +380,11 @@ __global__ __launch_bounds__(256) void k_colg_syn(ColParams p, GenParams gp) {
   }
 }
 
-__device__ void colg_finish(const ColParams& p, const GenParams& gp, float2* acc, float2* b1, int strip, int l) {
+__global__ __launch_bounds__(256) void k_colg_syn(ColParams p, GenParams gp) {
+  colg_syn_body(p, gp, own_block());
+}
+
+__device__ __forceinline__ void colg_finish(const ColParams& p, const GenParams& gp, float2* acc, float2* b1, int strip, int l) {
   const int n = gp.n, E = n * kGW, M = n / 2;
   for (int e = threadIdx.x; e < E; e += 256) acc[e] = make_float2(acc[e].x * p.inv_n2, acc[e].y * p.inv_n2);
   __syncthreads();
@@ -381,15 +394,15 @@ __device__ void colg_finish(const ColParams& p, const GenParams& gp, float2* acc
     if (strip * kGW + (e % kGW) <= M) o[e] = r[e];
 }
 
-__global__ __launch_bounds__(256) void k_colg_ana(ColParams p, GenParams gp) {
+__device__ __forceinline__ void colg_ana_body(const ColParams& p, const GenParams& gp, BlockId bid) {
   extern __shared__ float2 gsm[];
   const int n = gp.n, E = n * kGW, M = n / 2;
   float2* ba = gsm;
   float2* b0 = gsm + E;
   float2* b1 = gsm + 2 * E;
   __shared__ ItemStage<kGW> stg;
-  const int4 it = p.items[blockIdx.x];
-  const int l = blockIdx.y;
+  const int4 it = p.items[bid.x];
+  const int l = bid.y;
   stage_item_g(p, it, M, stg);
   for (int e = threadIdx.x; e < E; e += 256) ba[e] = make_float2(0.f, 0.f);
   __syncthreads();
@@ -416,21 +429,29 @@ __global__ __launch_bounds__(256) void k_colg_ana(ColParams p, GenParams gp) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_colg_final(ColParams p, GenParams gp) {
+__global__ __launch_bounds__(256) void k_colg_ana(ColParams p, GenParams gp) {
+  colg_ana_body(p, gp, own_block());
+}
+
+__device__ __forceinline__ void colg_final_body(const ColParams& p, const GenParams& gp, BlockId bid) {
   extern __shared__ float2 gsm[];
   const int n = gp.n, E = n * kGW;
-  const int2 si = p.strips[blockIdx.x];
+  const int2 si = p.strips[bid.x];
   if (si.y <= 1) return;
   float2* ba = gsm;
   float2* b1 = gsm + E;
-  const int l = blockIdx.y;
+  const int l = bid.y;
   for (int e = threadIdx.x; e < E; e += 256) ba[e] = make_float2(0.f, 0.f);
   for (int i = 0; i < si.y; ++i) {
     const float2* in = p.part + ((long long)p.items[si.x + i].w * p.labels + l) * E;
     for (int e = threadIdx.x; e < E; e += 256) ba[e] = make_float2(ba[e].x + in[e].x, ba[e].y + in[e].y);
   }
   __syncthreads();
-  colg_finish(p, gp, ba, b1, blockIdx.x, l);
+  colg_finish(p, gp, ba, b1, bid.x, l);
+}
+
+__global__ __launch_bounds__(256) void k_colg_final(ColParams p, GenParams gp) {
+  colg_final_body(p, gp, own_block());
 }
 
 }  // namespace shs

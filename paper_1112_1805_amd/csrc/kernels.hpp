@@ -300,6 +300,13 @@ struct PlaneBuf {
   }
 };
 
+// Block coordinates of a kernel body: its own grid's blockIdx.x / blockIdx.y / gridDim.x,
+// or the block's place inside one image's part of a grouped launch (see grouped.hpp).
+struct BlockId {
+  int x, y, gx;
+};
+__device__ __forceinline__ BlockId own_block() { return BlockId{int(blockIdx.x), int(blockIdx.y), int(gridDim.x)}; }
+
 // ---------------------------------------------------------------- row pass
 enum RowMode { ROW_SOLVE = 0, ROW_C2R = 1, ROW_R2C = 2, ROW_PRIME = 3, ROW_ENERGY = 4, ROW_SHRINK = 5, ROW_PD = 6 };
 
@@ -472,7 +479,7 @@ __device__ __forceinline__ void row_r2c(cpx (&a)[RowGeom<N>::R], float2* __restr
 }
 
 template <int N, int MODE, int ST, bool STATS>
-__global__ __launch_bounds__(RowGeom<N>::THREADS) void k_row(RowParams p) {
+__device__ __forceinline__ void row_body(const RowParams& p, BlockId bid) {
   using G = RowGeom<N>;
   using S = Store<ST>;
   __shared__ float2 lds[G::RPB * G::LROW];
@@ -481,8 +488,8 @@ __global__ __launch_bounds__(RowGeom<N>::THREADS) void k_row(RowParams p) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane / G::T, t = lane % G::T;
   const int rowl = wave * G::RPW + sub;
-  const int row = blockIdx.x * G::RPB + rowl;
-  const int ch = blockIdx.y;
+  const int row = bid.x * G::RPB + rowl;
+  const int ch = bid.y;
   const int j = ch % p.eta;
   const RowAddr<G::R> A{lds + rowl * G::LROW};
   cpx a[G::R];
@@ -603,10 +610,15 @@ __global__ __launch_bounds__(RowGeom<N>::THREADS) void k_row(RowParams p) {
     d[SLOT_L1] *= double(p.fw.lam[j]);
     block_sum4<G::WAVES>(d, red);
     if (threadIdx.x == 0) {
-      double* o = p.partials + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * 4;
+      double* o = p.partials + ((long long)bid.y * bid.gx + bid.x) * 4;
       o[0] = d[0]; o[1] = d[1]; o[2] = d[2]; o[3] = d[3];
     }
   }
+}
+
+template <int N, int MODE, int ST, bool STATS>
+__global__ __launch_bounds__(RowGeom<N>::THREADS) void k_row(RowParams p) {
+  row_body<N, MODE, ST, STATS>(p, own_block());
 }
 
 // ---------------------------------------------------------------- column passes
@@ -677,16 +689,16 @@ __device__ __forceinline__ float psi_at(const ColParams& p, int4 win, int k0) {
 
 // Dense column FFT of per-label spectra: U_l = colFFT(V_l) (forward) on every column.
 template <int N>
-__global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_col_fwd(ColParams p) {
+__device__ __forceinline__ void col_fwd_body(const ColParams& p, BlockId bid) {
   using G = ColCfg<N>;
   constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
   __shared__ float2 lds[col_lds_points<N, R>() * W];
   const int c = threadIdx.x % W, t = threadIdx.x / W;
-  const int k1 = blockIdx.x * W + c;
+  const int k1 = bid.x * W + c;
   const bool valid = k1 <= M;
-  const int l = blockIdx.y;
+  const int l = bid.y;
   const ColAddr<W, R> A{lds + c};
-  const long long strip = l * (long long)N * p.P + (long long)blockIdx.x * (N * W) + c;
+  const long long strip = l * (long long)N * p.P + (long long)bid.x * (N * W) + c;
   cpx a[R];
   static_for<R>([&](auto r) { a[r] = valid ? ld(p.in + strip + (t + r * T) * W) : cpx{0.f, 0.f}; });
   fft_run<N, R, G::RM, false, SYNC_BLOCK>(a, A, t, p.tw + col_sw_off<N>());
@@ -695,20 +707,25 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per
   }
 }
 
+template <int N>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_col_fwd(ColParams p) {
+  col_fwd_body<N>(p, own_block());
+}
+
 // Synthesis: for every filter j of the item, T1[l, j] = colIFFT(psi_j * U_l / N^2) on the
 // item's strip (only columns inside filter j's range exist in T1).  With PREFETCH the next
 // filter's values are loaded while the current inverse FFT runs.
 template <int N>
-__global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(ColGeom<N>::WPE))) void k_col_syn(ColParams p) {
+__device__ __forceinline__ void col_syn_body(const ColParams& p, BlockId bid) {
   using G = ColCfg<N>;
   constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
   __shared__ float2 lds[col_lds_points<N, R>() * W];
   __shared__ ItemStage<W> stg;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
-  const int4 it = p.items[blockIdx.x];
+  const int4 it = p.items[bid.x];
   const int k1 = it.x * W + c;
   const bool valid = k1 <= M;
-  const int l = blockIdx.y;
+  const int l = bid.y;
   const ColAddr<W, R> A{lds + c};
   stage_item<N>(p, it, stg);
   cpx uh[R];
@@ -735,6 +752,11 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per
 }
 
 template <int N>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(ColGeom<N>::WPE))) void k_col_syn(ColParams p) {
+  col_syn_body<N>(p, own_block());
+}
+
+template <int N>
 __device__ __forceinline__ void col_finish(const ColParams& p, cpx (&acc)[ColCfg<N>::R], int t, int k1, bool valid,
                                            int l, const ColAddr<ColCfg<N>::W, ColCfg<N>::R>& A) {
   using G = ColCfg<N>;
@@ -752,16 +774,16 @@ __device__ __forceinline__ void col_finish(const ColParams& p, cpx (&acc)[ColCfg
 // accumulator is stored and k_col_final sums the strip's items in order.  With PREFETCH
 // the next filter's spectrum column is loaded while the current FFT runs.
 template <int N>
-__global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(ColGeom<N>::WPE))) void k_col_ana(ColParams p) {
+__device__ __forceinline__ void col_ana_body(const ColParams& p, BlockId bid) {
   using G = ColCfg<N>;
   constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
   __shared__ float2 lds[col_lds_points<N, R>() * W];
   __shared__ ItemStage<W> stg;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
-  const int4 it = p.items[blockIdx.x];
+  const int4 it = p.items[bid.x];
   const int k1 = it.x * W + c;
   const bool valid = k1 <= M;
-  const int l = blockIdx.y;
+  const int l = bid.y;
   const ColAddr<W, R> A{lds + c};
   stage_item<N>(p, it, stg);
   __syncthreads();
@@ -798,16 +820,21 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per
 }
 
 template <int N>
-__global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_col_final(ColParams p) {
+__global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(ColGeom<N>::WPE))) void k_col_ana(ColParams p) {
+  col_ana_body<N>(p, own_block());
+}
+
+template <int N>
+__device__ __forceinline__ void col_final_body(const ColParams& p, BlockId bid) {
   using G = ColCfg<N>;
   constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
   __shared__ float2 lds[col_lds_points<N, R>() * W];
-  const int2 si = p.strips[blockIdx.x];
+  const int2 si = p.strips[bid.x];
   if (si.y <= 1) return;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
-  const int k1 = blockIdx.x * W + c;
+  const int k1 = bid.x * W + c;
   const bool valid = k1 <= M;
-  const int l = blockIdx.y;
+  const int l = bid.y;
   const ColAddr<W, R> A{lds + c};
   cpx acc[R];
   static_for<R>([&](auto r) { acc[r] = cpx{0.f, 0.f}; });
@@ -817,6 +844,11 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per
     static_for<R>([&](auto r) { acc[r] = acc[r] + ld(in + (t + r * T) * W + c); });
   }
   col_finish<N>(p, acc, t, k1, valid, l, A);
+}
+
+template <int N>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_col_final(ColParams p) {
+  col_final_body<N>(p, own_block());
 }
 
 // ---------------------------------------------------------------- plan-time filter windows
@@ -898,10 +930,10 @@ __device__ __forceinline__ void simplex_project(float (&g)[MQ], int q) {
 // u = 1/2 [z + (w - b_w) - gamma s]  (Section 3 u-update, A^T A = 2I);
 // g_w = b_w + u;  w = P_C(g_w) (pixelwise simplex);  b_w = g_w - w.
 template <bool STATS, bool HAVE_Z>
-__global__ __launch_bounds__(256) void k_pixel(PixParams p) {
+__device__ __forceinline__ void pixel_body(const PixParams& p, BlockId bid) {
   constexpr int MQ = 8;
   __shared__ double red[4 * 4];
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long i = (long long)bid.x * 256 + threadIdx.x;
   const bool active = i < p.n2;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (active) {
@@ -939,10 +971,15 @@ __global__ __launch_bounds__(256) void k_pixel(PixParams p) {
   if constexpr (STATS) {
     block_sum4<4>(acc, red);
     if (threadIdx.x == 0) {
-      double* o = p.partials + (long long)blockIdx.x * 4;
+      double* o = p.partials + (long long)bid.x * 4;
       o[0] = acc[0]; o[1] = acc[1]; o[2] = acc[2]; o[3] = acc[3];
     }
   }
+}
+
+template <bool STATS, bool HAVE_Z>
+__global__ __launch_bounds__(256) void k_pixel(PixParams p) {
+  pixel_body<STATS, HAVE_Z>(p, own_block());
 }
 
 // Primal step of the primal-dual iteration: u_new = P_C(u - tau (K^T y + s)) and the

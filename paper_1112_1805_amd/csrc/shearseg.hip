@@ -15,6 +15,7 @@
 #include "shearseg.h"
 #include "kernels.hpp"
 #include "generic.hpp"
+#include "grouped.hpp"
 #include "tv.hpp"
 #include "nl.hpp"
 
@@ -255,6 +256,51 @@ Layout make_layout(const shs_plan* p) {
   return L;
 }
 
+// ---------------------------------------------------------------- launch recording (batches)
+// While a Recorder is installed (this thread), the launchers below append a description of
+// each launch, with the grouped kernel of its configuration, instead of launching; the
+// batch solve turns one iteration's records of all images into grouped launches.  Each
+// record carries the step of the iteration it belongs to.
+enum BatchStep { BS_ANA, BS_FINAL, BS_C2R, BS_PIXEL, BS_R2C, BS_FWD, BS_SYN, BS_ROW, BS_REDUCE, BS_COUNT };
+enum RecKind { RK_ROW, RK_COL, RK_PIX, RK_REDUCE };
+struct LaunchRec {
+  int step = 0, kind = 0;
+  const void* fn = nullptr;    // grouped kernel of the launch's configuration
+  int threads = 0, gx = 0, gy = 0;
+  size_t lds = 0;              // dynamic LDS bytes
+  RowParams rp{};
+  ColParams cp{};
+  PixParams pp{};
+  GenParams gp{};
+  // RK_REDUCE (one image's two-level FP64 reduction)
+  double* parts = nullptr;
+  long long nparts = 0;
+  double* red1 = nullptr;
+  double* sdev = nullptr;
+  double gamma = 1.0;
+};
+struct Recorder {
+  std::vector<LaunchRec> recs;
+  int step = 0;
+};
+thread_local Recorder* g_rec = nullptr;
+void rec_step(int s) {
+  if (g_rec) g_rec->step = s;
+}
+template <class F>
+LaunchRec& rec_add(int kind, F fn, int threads, int gx, int gy, size_t lds) {
+  LaunchRec r;
+  r.step = g_rec->step;
+  r.kind = kind;
+  r.fn = reinterpret_cast<const void*>(fn);
+  r.threads = threads;
+  r.gx = gx;
+  r.gy = gy;
+  r.lds = lds;
+  g_rec->recs.push_back(r);
+  return g_rec->recs.back();
+}
+
 // ---------------------------------------------------------------- per-size launchers
 template <int N>
 struct Pipe {
@@ -264,6 +310,10 @@ struct Pipe {
   template <int MODE, int ST, bool STATS>
   static void row_t(const RowParams& rp, int channels, hipStream_t s) {
     dim3 grid(N / RG::RPB, channels);
+    if (g_rec) {
+      rec_add(RK_ROW, &kg_row<N, MODE, ST, STATS>, RG::THREADS, N / RG::RPB, channels, 0).rp = rp;
+      return;
+    }
     hipLaunchKernelGGL((k_row<N, MODE, ST, STATS>), grid, dim3(RG::THREADS), 0, s, rp);
   }
   static void row(const shs_plan*, int mode, int store, bool stats, const RowParams& rp, int channels, hipStream_t s) {
@@ -291,6 +341,17 @@ struct Pipe {
   }
   static void col(const shs_plan*, int kind, const ColParams& cp, int nblocks, int labels, hipStream_t s) {
     const dim3 grid(nblocks, labels), block(CG::THREADS);
+    if (g_rec) {
+      LaunchRec* r = nullptr;
+      switch (kind) {
+        case 0: r = &rec_add(RK_COL, &kg_col_fwd<N>, CG::THREADS, nblocks, labels, 0); break;
+        case 1: r = &rec_add(RK_COL, &kg_col_syn<N>, CG::THREADS, nblocks, labels, 0); break;
+        case 2: r = &rec_add(RK_COL, &kg_col_ana<N>, CG::THREADS, nblocks, labels, 0); break;
+        case 3: r = &rec_add(RK_COL, &kg_col_final<N>, CG::THREADS, nblocks, labels, 0); break;
+      }
+      if (r) r->cp = cp;
+      return;
+    }
     switch (kind) {
       case 0: hipLaunchKernelGGL((k_col_fwd<N>), grid, block, 0, s, cp); break;
       case 1: hipLaunchKernelGGL((k_col_syn<N>), grid, block, 0, s, cp); break;
@@ -309,6 +370,17 @@ struct GenPipe {
     // 4 waves per block, p->rw rows per wave
     const dim3 grid(p->n / p->rpb, channels);
     const size_t lds = size_t(4) * 2 * p->M * p->rw * sizeof(float2);
+    if (g_rec) {
+      LaunchRec* r = nullptr;
+      switch (p->rw) {
+        case 4: r = &rec_add(RK_ROW, &kg_row_g<MODE, ST, STATS, 4>, 256, p->n / p->rpb, channels, lds); break;
+        case 2: r = &rec_add(RK_ROW, &kg_row_g<MODE, ST, STATS, 2>, 256, p->n / p->rpb, channels, lds); break;
+        default: r = &rec_add(RK_ROW, &kg_row_g<MODE, ST, STATS, 1>, 256, p->n / p->rpb, channels, lds); break;
+      }
+      r->rp = rp;
+      r->gp = gp(p);
+      return;
+    }
     switch (p->rw) {
       case 4: hipLaunchKernelGGL((k_row_g<MODE, ST, STATS, 4>), grid, dim3(256), lds, s, rp, gp(p)); break;
       case 2: hipLaunchKernelGGL((k_row_g<MODE, ST, STATS, 2>), grid, dim3(256), lds, s, rp, gp(p)); break;
@@ -342,6 +414,20 @@ struct GenPipe {
   static void col(const shs_plan* p, int kind, const ColParams& cp, int nblocks, int labels, hipStream_t s) {
     const dim3 grid(nblocks, labels), block(256);
     const size_t e = size_t(p->n) * kGW * sizeof(float2);
+    if (g_rec) {
+      LaunchRec* r = nullptr;
+      switch (kind) {
+        case 0: r = &rec_add(RK_COL, &kg_colg_fwd, 256, nblocks, labels, 2 * e); break;
+        case 1: r = &rec_add(RK_COL, &kg_colg_syn, 256, nblocks, labels, 3 * e); break;
+        case 2: r = &rec_add(RK_COL, &kg_colg_ana, 256, nblocks, labels, 3 * e); break;
+        case 3: r = &rec_add(RK_COL, &kg_colg_final, 256, nblocks, labels, 2 * e); break;
+      }
+      if (r) {
+        r->cp = cp;
+        r->gp = gp(p);
+      }
+      return;
+    }
     switch (kind) {
       case 0: hipLaunchKernelGGL(k_colg_fwd, grid, block, 2 * e, s, cp, gp(p)); break;
       case 1: hipLaunchKernelGGL(k_colg_syn, grid, block, 3 * e, s, cp, gp(p)); break;
@@ -519,14 +605,17 @@ void enqueue_synthesis(const Ctx& c, const float* real_in, int count) {
   rp.real_in = real_in;
   rp.spec_out = c.at<float2>(c.L.v);
   rp.lout = dense_layout(p);
+  rec_step(BS_R2C);
   run_row(c, ROW_R2C, ST_F32, false, rp, count);
   ColParams cp = col_params(c, count);
   cp.in = c.at<float2>(c.L.v);
   cp.out = c.at<float2>(c.L.v);          // column FFT in place: V -> U
+  rec_step(BS_FWD);
   run_col(c, COL_FWD, cp, p->NS, count);
   cp.in = c.at<float2>(c.L.v);
   cp.out = c.at<float2>(c.L.t1);
   cp.items = p->items_syn;
+  rec_step(BS_SYN);
   run_col(c, COL_SYN, cp, p->n_syn, count);
 }
 
@@ -537,13 +626,25 @@ void enqueue_analysis(const Ctx& c, int count) {
   cp.in = c.at<float2>(c.L.t2);
   cp.out = c.at<float2>(c.L.z);
   cp.items = p->items_ana;
+  rec_step(BS_ANA);
   run_col(c, COL_ANA, cp, p->n_ana, count);
+  rec_step(BS_FINAL);
   if (p->n_part > 0) run_col(c, COL_FINAL, cp, p->NS, count);
 }
 
 // hist_ctr: NULL (hist_row is the row itself) or the device row counter (hist_row is the
 // history's first row).
 void enqueue_reduce(const Ctx& c, long long nparts, double* hist_row, double gamma, int* hist_ctr = nullptr) {
+  if (g_rec) {
+    rec_step(BS_REDUCE);
+    LaunchRec& r = rec_add(RK_REDUCE, &k_reduce2, 256, 1, 1, 0);
+    r.parts = c.at<double>(c.L.parts);
+    r.nparts = nparts;
+    r.red1 = c.at<double>(c.L.red1);
+    r.sdev = c.at<double>(c.L.sdev);
+    r.gamma = gamma;
+    return;
+  }
   Timed tm(c.s, KC_REDUCE);
   const long long per = (nparts + kRed1Blocks - 1) / kRed1Blocks;
   hipLaunchKernelGGL(k_reduce1, dim3(kRed1Blocks), dim3(256), 0, c.s, c.at<double>(c.L.parts), nparts,
@@ -750,6 +851,7 @@ void enqueue_iteration(const Ctx& c, const float* d_s, float gamma, bool have_ad
     rz.spec_in = c.at<float2>(L.z);
     rz.lin = dense_layout(p);
     rz.real_out = c.at<float>(L.zs);
+    rec_step(BS_C2R);
     run_row(c, ROW_C2R, ST_F32, false, rz, q);
   }
   PixParams pp{};
@@ -762,7 +864,12 @@ void enqueue_iteration(const Ctx& c, const float* d_s, float gamma, bool have_ad
   pp.n2 = n2;
   pp.gamma = gamma;
   pp.q = q;
-  {
+  rec_step(BS_PIXEL);
+  if (g_rec) {
+    auto fn = have_adjoint_input ? (stats ? &kg_pixel<true, true> : &kg_pixel<false, true>)
+                                 : (stats ? &kg_pixel<true, false> : &kg_pixel<false, false>);
+    rec_add(RK_PIX, fn, 256, int(npix_blocks), 1, 0).pp = pp;
+  } else {
     Timed tm(c.s, KC_PIXEL);
     const dim3 g{unsigned(npix_blocks)}, b{256};
     if (have_adjoint_input) {
@@ -781,6 +888,7 @@ void enqueue_iteration(const Ctx& c, const float* d_s, float gamma, bool have_ad
   rp.lout = pruned_layout(p);
   rp.g = c.ws + L.g;
   rp.emit = emit ? 1 : 0;
+  rec_step(BS_ROW);
   run_row(c, ROW_SOLVE, p->store, stats, rp, q * p->eta);
   if (stats) enqueue_reduce(c, L.nrow_parts + npix_blocks, hist_row, gamma, hist_ctr);
 }
@@ -929,58 +1037,143 @@ void launch_nl(bool stats, long long npix, hipStream_t s, const NlParams& p) {
 
 }  // namespace
 
-constexpr int kBatchStreams = 8;   // internal streams of a batch (default priority)
-
 // A batch of images of different sizes and label counts (one plan per distinct shape).
-// Every iteration of all images is one captured graph (images forked over internal
-// streams so that small images run side by side), replayed on the caller's stream.
+// A solve of the whole batch is one captured graph, replayed on the caller's stream with a
+// single launch.  Images are split into lanes by kernel class (the same kernels and the same
+// occupancy); in a lane every step of an iteration is one grouped launch covering all its
+// images (grouped.hpp), and the lanes are independent branches of the graph that run side by
+// side.
 struct shs_batch {
   int count = 0, device = 0;
   std::vector<shs_plan*> plans;
   std::vector<int> plan_of;
-  std::vector<int> stream_of;   // stream of each image (longest-first greedy balance)
-  std::vector<int> order;       // images by decreasing estimated cost (capture order)
   std::vector<size_t> ws_off;
   size_t ws_total = 0;
-  std::vector<hipStream_t> streams;
-  std::vector<hipEvent_t> join;
-  hipStream_t main = nullptr;
+  std::vector<std::vector<int>> lanes; // images by kernel class (see batch_class)
+  hipStream_t main = nullptr;          // capture stream (default priority)
+  std::vector<hipStream_t> lane_s;     // one capture branch per lane (default priority)
+  std::vector<hipEvent_t> lane_e;
   hipEvent_t fork = nullptr;
-  std::vector<double> key;
-  hipGraphExec_t g_init = nullptr, g_first = nullptr, g_mid = nullptr, g_last = nullptr;
+  std::vector<double> key;             // pointers and parameters baked into the graph
+  hipGraphExec_t graph = nullptr;      // the whole solve
+  void* arena = nullptr;               // device task tables of the grouped launches
 
-  void drop_graphs() {
-    for (hipGraphExec_t* g : {&g_init, &g_first, &g_mid, &g_last})
-      if (*g) { (void)hipGraphExecDestroy(*g); *g = nullptr; }
+  void drop_graph() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    graph = nullptr;
+    if (arena) (void)hipFree(arena);
+    arena = nullptr;
     key.clear();
-  }
-  // Captures `body` (which enqueues on the internal streams) into an executable graph.
-  template <class F>
-  shs_status capture(F&& body, hipGraphExec_t* out) {
-    CaptureScope cs;
-    HIPCHK(hipStreamBeginCapture(main, hipStreamCaptureModeThreadLocal));
-    bool ok = hipEventRecord(fork, main) == hipSuccess;
-    for (hipStream_t s : streams) ok = ok && hipStreamWaitEvent(s, fork, 0) == hipSuccess;
-    if (ok) body();
-    ok = ok && hipGetLastError() == hipSuccess;
-    for (size_t k = 0; k < streams.size(); ++k) {
-      ok = ok && hipEventRecord(join[k], streams[k]) == hipSuccess;
-      ok = ok && hipStreamWaitEvent(main, join[k], 0) == hipSuccess;
-    }
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(main, &g);
-    if (!ok || e != hipSuccess || !g) {
-      if (g) (void)hipGraphDestroy(g);
-      return fail(SHS_E_DEVICE, "graph capture failed");
-    }
-    const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (ei != hipSuccess) return fail(SHS_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
-    return SHS_OK;
   }
 };
 
 namespace {
+// One iteration of a batch as launches: grouped launches (tables at arena offsets) and the
+// per-image FP64 reductions, in the order of the iteration's steps.
+struct BatchItem {
+  bool group = true;
+  const void* fn = nullptr;
+  int threads = 0;
+  size_t lds = 0;
+  unsigned blocks = 0;
+  size_t tasks_off = 0, bt_off = 0;
+  LaunchRec red;       // !group: one image's reduction
+};
+using BatchIter = std::vector<BatchItem>;
+
+size_t arena_put(std::vector<char>& a, const void* data, size_t bytes) {
+  const size_t off = align256(a.size());
+  a.resize(off + bytes);
+  std::memcpy(a.data() + off, data, bytes);
+  return off;
+}
+
+template <class P>
+void put_group(const std::vector<const LaunchRec*>& recs, P LaunchRec::*field, std::vector<char>& arena,
+               BatchItem& it) {
+  std::vector<GroupTask<P>> tasks(recs.size());
+  std::vector<uint16_t> bt;
+  unsigned start = 0;
+  for (size_t k = 0; k < recs.size(); ++k) {
+    const LaunchRec& r = *recs[k];
+    GroupTask<P>& T = tasks[k];
+    std::memset(static_cast<void*>(&T), 0, sizeof(T));
+    T.p = r.*field;
+    T.gp = r.gp;
+    T.gx = r.gx;
+    T.gy = r.gy;
+    T.start = int(start);
+    const unsigned nb = unsigned(r.gx) * unsigned(r.gy);
+    bt.insert(bt.end(), nb, uint16_t(k));
+    start += nb;
+    it.lds = std::max(it.lds, r.lds);
+  }
+  it.blocks = start;
+  it.tasks_off = arena_put(arena, tasks.data(), tasks.size() * sizeof(GroupTask<P>));
+  it.bt_off = arena_put(arena, bt.data(), bt.size() * sizeof(uint16_t));
+}
+
+// Groups one iteration's records of all images (image order) by step, then by kernel.
+void build_batch_iter(const std::vector<LaunchRec>& recs, std::vector<char>& arena, BatchIter& out) {
+  for (int step = 0; step < BS_COUNT; ++step) {
+    std::vector<std::pair<const void*, int>> keys;
+    std::vector<std::vector<const LaunchRec*>> groups;
+    for (const LaunchRec& r : recs) {
+      if (r.step != step) continue;
+      if (r.kind == RK_REDUCE) {
+        BatchItem it;
+        it.group = false;
+        it.red = r;
+        out.push_back(it);
+        continue;
+      }
+      size_t g = 0;
+      while (g < keys.size() && !(keys[g].first == r.fn && keys[g].second == r.threads)) ++g;
+      if (g == keys.size()) {
+        keys.emplace_back(r.fn, r.threads);
+        groups.emplace_back();
+      }
+      groups[g].push_back(&r);
+    }
+    for (size_t g = 0; g < groups.size(); ++g) {
+      BatchItem it;
+      it.fn = keys[g].first;
+      it.threads = keys[g].second;
+      const int kind = groups[g][0]->kind;
+      if (kind == RK_ROW) put_group(groups[g], &LaunchRec::rp, arena, it);
+      else if (kind == RK_COL) put_group(groups[g], &LaunchRec::cp, arena, it);
+      else put_group(groups[g], &LaunchRec::pp, arena, it);
+      out.push_back(it);
+    }
+  }
+}
+
+// Kernel class of an image: the power-of-two side, or for the mixed-radix path the rows per
+// wave of its row pass and the blocks per CU its column passes' LDS allows (a grouped launch
+// takes its largest image's LDS, so only images of one occupancy share a launch).
+int batch_class(const shs_plan* p) {
+  if (!p->generic) return p->n;
+  const int lds3 = 3 * p->n * kGW * int(sizeof(float2));
+  const int bpc = std::min(4, (160 * 1024) / lds3);
+  return 100000 + p->rw * 10 + bpc;
+}
+
+void launch_batch_iter(const BatchIter& iter, char* dbase, hipStream_t s) {
+  for (const BatchItem& it : iter) {
+    if (it.group) {
+      void* tasks = dbase + it.tasks_off;
+      void* bt = dbase + it.bt_off;
+      void* args[] = {&tasks, &bt};
+      (void)hipLaunchKernel(it.fn, dim3(it.blocks), dim3(it.threads), args, it.lds, s);
+    } else {
+      const LaunchRec& r = it.red;
+      const long long per = std::max<long long>((r.nparts + kRed1Blocks - 1) / kRed1Blocks, 1);
+      hipLaunchKernelGGL(k_reduce1, dim3(kRed1Blocks), dim3(256), 0, s, r.parts, r.nparts, per, r.red1);
+      hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(256), 0, s, r.red1, kRed1Blocks, r.sdev, nullptr, r.gamma,
+                         nullptr);
+    }
+  }
+}
 }  // namespace
 
 // ---------------------------------------------------------------- graph replay
@@ -1251,6 +1444,14 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colg_final), hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds2) != hipSuccess ||
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colg_solve), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds2) != hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&kg_colg_syn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds3) != hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&kg_colg_ana), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds3) != hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&kg_colg_fwd), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds2) != hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&kg_colg_final), hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds2) != hipSuccess) {
       free_plan(p);
       return fail(SHS_E_DEVICE, "cannot reserve LDS for the mixed-radix column passes");
@@ -1750,6 +1951,7 @@ shs_status shs_solve_noalloc(const shs_plan* p, const shs_params* prm, const flo
 
 shs_status shs_batch_create(int32_t count, const shs_shape* shapes, int device, shs_batch** out) {
   if (!out || !shapes || count < 1) return fail(SHS_E_INVALID, "null argument or count < 1");
+  if (count > 65535) return fail(SHS_E_UNSUPPORTED, "at most 65535 images per batch");
   *out = nullptr;
   shs_batch* b = new (std::nothrow) shs_batch{};
   if (!b) return fail(SHS_E_NOMEM, "host allocation");
@@ -1777,39 +1979,31 @@ shs_status shs_batch_create(int32_t count, const shs_shape* shapes, int device, 
     b->ws_off.push_back(b->ws_total);
     b->ws_total += align256(shs_workspace_bytes(b->plans[found]));
   }
-  DeviceGuard dg(device);
-  const int nstreams = std::min(count, kBatchStreams);
-  // Balance the streams: an iteration of the batch ends with its slowest stream.  Cost of
-  // an image ~ q eta N^2 log2 N (the mixed-radix path costs about twice as much per
-  // coefficient); largest first onto the least loaded stream.
   {
-    std::vector<double> cost(count), load(nstreams, 0.0);
+    std::vector<int> keys;
     for (int i = 0; i < count; ++i) {
-      const shs_plan* p = b->plans[b->plan_of[i]];
-      cost[i] = double(p->q) * p->eta * double(p->n) * p->n * std::log2(double(p->n)) * (p->generic ? 2.0 : 1.0);
-      b->order.push_back(i);
-    }
-    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-    b->stream_of.assign(count, 0);
-    for (int i : b->order) {
-      const int k = int(std::min_element(load.begin(), load.end()) - load.begin());
-      b->stream_of[i] = k;
-      load[k] += cost[i];
+      const int k = batch_class(b->plans[b->plan_of[i]]);
+      size_t l = 0;
+      while (l < keys.size() && keys[l] != k) ++l;
+      if (l == keys.size()) {
+        keys.push_back(k);
+        b->lanes.emplace_back();
+      }
+      b->lanes[l].push_back(i);
     }
   }
-  for (int k = 0; k < nstreams; ++k) {
-    hipStream_t s;
-    hipEvent_t e;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-      shs_batch_destroy(b);
-      return fail(SHS_E_DEVICE, "batch stream creation");
-    }
-    b->streams.push_back(s);
-    b->join.push_back(e);
+  DeviceGuard dg(device);
+  bool ok = hipStreamCreateWithFlags(&b->main, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+  for (size_t l = 0; ok && l < b->lanes.size(); ++l) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+    if (st) b->lane_s.push_back(st);
+    if (ev) b->lane_e.push_back(ev);
   }
-  if (hipStreamCreateWithFlags(&b->main, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
+  if (!ok) {
     shs_batch_destroy(b);
     return fail(SHS_E_DEVICE, "batch stream creation");
   }
@@ -1820,11 +2014,11 @@ shs_status shs_batch_create(int32_t count, const shs_shape* shapes, int device, 
 shs_status shs_batch_destroy(shs_batch* b) {
   if (!b) return SHS_OK;
   DeviceGuard dg(b->device);
-  b->drop_graphs();
-  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
-  for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+  b->drop_graph();
   if (b->main) (void)hipStreamDestroy(b->main);
   if (b->fork) (void)hipEventDestroy(b->fork);
+  for (hipStream_t st : b->lane_s) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : b->lane_e) (void)hipEventDestroy(ev);
   for (shs_plan* p : b->plans) shs_plan_destroy(p);
   delete b;
   return SHS_OK;
@@ -1847,16 +2041,16 @@ shs_status shs_solve_batch(shs_batch* b, const shs_params* params, const float* 
     if (params[i].tol != 0.0 || params[i].resume) return fail(SHS_E_UNSUPPORTED, "batch solves take no tol / resume");
   }
   DeviceGuard dg(b->device);
-  // per-image contexts
+  // per-image contexts, all on the capture stream
   std::vector<Ctx> ctx(b->count);
   for (int i = 0; i < b->count; ++i) {
     const shs_plan* p = b->plans[b->plan_of[i]];
     shs_status st = make_ctx(p, static_cast<char*>(d_ws) + b->ws_off[i], shs_workspace_bytes(p), nullptr, ctx[i]);
     if (st == SHS_OK) st = set_lambda(ctx[i], &params[i]);
     if (st != SHS_OK) return fail(st, "image " + std::to_string(i) + ": " + g_err);
-    ctx[i].s = b->streams[b->stream_of[i]];
+    ctx[i].s = b->main;
   }
-  // graph cache key: every pointer and parameter baked into the graphs
+  // graph cache key: every pointer and parameter baked into the graph
   std::vector<double> key;
   key.push_back(double(reinterpret_cast<uintptr_t>(d_ws)));
   key.push_back(double(reinterpret_cast<uintptr_t>(d_stats)));
@@ -1868,8 +2062,35 @@ shs_status shs_solve_batch(shs_batch* b, const shs_params* params, const float* 
     key.push_back(params[i].gamma);
     for (int f = 0; f < ctx[i].p->eta; ++f) key.push_back(ctx[i].fw.lam[f]);
   }
-  if (key != b->key) {
-    b->drop_graphs();
+  if (key != b->key || !b->graph) {
+    b->drop_graph();
+    // the iteration variants, recorded for all images and grouped
+    struct Variant {
+      bool adj, stats, emit;
+    };
+    std::vector<Variant> vars;
+    if (iters == 1) vars = {{false, true, false}};
+    else if (iters == 2) vars = {{false, false, true}, {true, true, false}};
+    else if (iters >= 3) vars = {{false, false, true}, {true, false, true}, {true, true, false}};
+    std::vector<char> arena;
+    const size_t nl = b->lanes.size();
+    std::vector<std::vector<BatchIter>> its(nl, std::vector<BatchIter>(vars.size()));
+    for (size_t l = 0; l < nl; ++l) {
+      for (size_t v = 0; v < vars.size(); ++v) {
+        Recorder rec;
+        CaptureScope cs;        // no timing events while recording
+        g_rec = &rec;
+        for (int i : b->lanes[l])
+          enqueue_iteration(ctx[i], d_s[i], params[i].gamma, vars[v].adj, vars[v].stats, vars[v].emit, nullptr);
+        g_rec = nullptr;
+        build_batch_iter(rec.recs, arena, its[l][v]);
+      }
+    }
+    if (!arena.empty()) {
+      if (hipMalloc(&b->arena, arena.size()) != hipSuccess) return fail(SHS_E_NOMEM, "batch task tables");
+      HIPCHK(hipMemcpy(b->arena, arena.data(), arena.size(), hipMemcpyHostToDevice));
+    }
+    char* dbase = static_cast<char*>(b->arena);
     auto tail = [&](int i) {   // epilogue + statistics of image i (zeros when no iteration ran)
       const Ctx& c = ctx[i];
       enqueue_epilogue(c, d_u ? d_u[i] : nullptr, d_labels ? d_labels[i] : nullptr);
@@ -1879,40 +2100,45 @@ shs_status shs_solve_batch(shs_batch* b, const shs_params* params, const float* 
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, c.s, reinterpret_cast<uint32_t*>(d_stats + 5LL * i),
                            10LL, 0u);
     };
-    shs_status st = SHS_OK;
-    if (st == SHS_OK) st = b->capture([&] { for (int i : b->order) enqueue_zero_state(ctx[i]); }, &b->g_init);
-    if (iters == 0) {
-      if (st == SHS_OK) st = b->capture([&] { for (int i : b->order) tail(i); }, &b->g_last);
-    } else if (iters == 1) {
-      if (st == SHS_OK)
-        st = b->capture([&] {
-          for (int i : b->order) { enqueue_iteration(ctx[i], d_s[i], params[i].gamma, false, true, false, nullptr); tail(i); }
-        }, &b->g_last);
-    } else {
-      if (st == SHS_OK)
-        st = b->capture([&] {
-          for (int i : b->order) enqueue_iteration(ctx[i], d_s[i], params[i].gamma, false, false, true, nullptr);
-        }, &b->g_first);
-      if (st == SHS_OK)
-        st = b->capture([&] {
-          for (int i : b->order) enqueue_iteration(ctx[i], d_s[i], params[i].gamma, true, false, true, nullptr);
-        }, &b->g_mid);
-      if (st == SHS_OK)
-        st = b->capture([&] {
-          for (int i : b->order) { enqueue_iteration(ctx[i], d_s[i], params[i].gamma, true, true, false, nullptr); tail(i); }
-        }, &b->g_last);
+    {
+      CaptureScope cs;
+      HIPCHK(hipStreamBeginCapture(b->main, hipStreamCaptureModeThreadLocal));
+      bool ok = hipEventRecord(b->fork, b->main) == hipSuccess;
+      for (size_t l = 0; ok && l < nl; ++l) {
+        hipStream_t ls = b->lane_s[l];
+        ok = hipStreamWaitEvent(ls, b->fork, 0) == hipSuccess;
+        for (int i : b->lanes[l]) {
+          ctx[i].s = ls;
+          enqueue_zero_state(ctx[i]);
+        }
+        if (iters >= 1) launch_batch_iter(its[l][0], dbase, ls);
+        for (int it = 1; it + 1 < iters; ++it) launch_batch_iter(its[l][1], dbase, ls);
+        if (iters >= 2) launch_batch_iter(its[l].back(), dbase, ls);
+        for (int i : b->lanes[l]) tail(i);
+        ok = ok && hipEventRecord(b->lane_e[l], ls) == hipSuccess &&
+             hipStreamWaitEvent(b->main, b->lane_e[l], 0) == hipSuccess;
+      }
+      const hipError_t el = ok ? hipGetLastError() : hipErrorUnknown;
+      hipGraph_t g = nullptr;
+      const hipError_t ee = hipStreamEndCapture(b->main, &g);
+      if (el != hipSuccess || ee != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        b->drop_graph();
+        return fail(SHS_E_DEVICE, "capture of the batch graph failed");
+      }
+      const hipError_t ei = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        b->graph = nullptr;
+        b->drop_graph();
+        return fail(SHS_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+      }
     }
-    if (st != SHS_OK) { b->drop_graphs(); return st; }
     b->key = key;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   Timed tm(s, KC_BATCH);
-  HIPCHK(hipGraphLaunch(b->g_init, s));
-  if (iters >= 2) {
-    HIPCHK(hipGraphLaunch(b->g_first, s));
-    for (int it = 1; it < iters - 1; ++it) HIPCHK(hipGraphLaunch(b->g_mid, s));
-  }
-  HIPCHK(hipGraphLaunch(b->g_last, s));
+  HIPCHK(hipGraphLaunch(b->graph, s));
   return SHS_OK;
 }
 

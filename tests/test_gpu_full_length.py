@@ -36,18 +36,24 @@ BOUNDS = {
     ("c4q3", "f16"): (1e-2, 1e-4),
     ("c4q3", "bf16"): (5e-2, 1e-3),
 }
-# Residual histories, median relative error over the run per quantity.  With FP32 state
-# every quantity follows the oracle.  With 16-bit state the stored g is rounded every
-# iteration, so once the run has converged far enough the changes ||dv|| (dual residual)
-# and with them the combined residual sit at the rounding level of g instead of shrinking
-# like the oracle's: those two are bounded loosely over the whole run and tightly over the
-# first 10% of the iterations, where they are far above that floor.
+# Residual histories, relative error per iteration: median over the run, and the largest
+# over the first 10% of the iterations.  With FP32 state every quantity follows the oracle.
+# With 16-bit state the stored g is rounded every iteration, and the changes ||dv|| (dual
+# residual, and through it the combined residual) contain that rounding: once the run has
+# converged they sit at the rounding level of g instead of shrinking like the oracle's, and
+# where the thresholds gamma lambda_j are small against |g| (the RGB workload: 0.004..0.08)
+# the rounding is a visible part of ||dv|| from the first iterations on.  Those two are
+# bounded loosely; the primal residual and the energy surrogate tightly.
 HIST_MEDIAN = {
     "f32": {"r_primal": 1e-3, "r_dual": 1e-3, "r_combined": 1e-3, "surrogate": 1e-5},
     "f16": {"r_primal": 1e-2, "r_dual": 0.5, "r_combined": 0.5, "surrogate": 1e-4},
     "bf16": {"r_primal": 5e-2, "r_dual": 2.0, "r_combined": 2.0, "surrogate": 1e-3},
 }
-HIST_EARLY = {"f32": 1e-3, "f16": 2e-2, "bf16": 1e-1}
+HIST_EARLY = {
+    "f32": {"r_primal": 1e-3, "r_dual": 1e-3, "r_combined": 1e-3, "surrogate": 1e-5},
+    "f16": {"r_primal": 1e-2, "r_dual": 0.1, "r_combined": 5e-2, "surrogate": 1e-4},
+    "bf16": {"r_primal": 5e-2, "r_dual": 1.0, "r_combined": 0.5, "surrogate": 1e-3},
+}
 WORKLOADS = {"c1": make_c1, "c2": make_c2, "c4q3": lambda: make_c4(q=3)}
 
 
@@ -128,7 +134,8 @@ def test_full_length_against_stored_oracle(case, store):
     assert dsum <= sum_max
     for key, bound in HIST_MEDIAN[store].items():
         assert herr[key] <= bound, (key, herr)
-    assert max(early.values()) <= HIST_EARLY[store], early
+    for key, bound in HIST_EARLY[store].items():
+        assert early[key] <= bound, (key, early)
     # the relaxed labelling lies in C and the labels are its argmax (lowest index on ties)
     assert np.all(r["u"] >= 0) and np.max(np.abs(r["u"].sum(axis=0) - 1)) < 1e-5
     assert np.array_equal(r["labels"], np.argmax(r["u"], axis=0))

@@ -633,9 +633,11 @@ def test_label_permutation_transpose_shift():
     assert np.max(np.abs(d["u"] - np.roll(a["u"], (5, -9), axis=(1, 2)))) < 2e-6
 
 
-@pytest.mark.parametrize("store", ["f32", "bf16"])
-def test_resume_bitwise(store):
-    w = make_small(128, 3, 3, seed=23, lam=0.1, iters=14)
+@pytest.mark.parametrize("store,n", [("f32", 128), ("bf16", 128), ("f16", 512), ("f32", 1024)])
+def test_resume_bitwise(store, n):
+    # n = 512 and 1024 run the two-rows-per-wavefront row pass (its restart primes the
+    # adjoint input from the stored state)
+    w = make_small(n, 3, 3, seed=23, lam=0.1, iters=14)
     full = run_gpu(w, store=store, hist=False)
     part = run_gpu(w, iters=9, store=store, hist=False)
     # checkpoint: copy the state prefix out, scribble, copy back, resume
