@@ -75,6 +75,7 @@ _SIGS = {
     "shs_plan_destroy": (_I32, [_VP]),
     "shs_workspace_bytes": (_SZ, [_VP]),
     "shs_state_bytes": (_SZ, [_VP]),
+    "shs_plan_describe": (ctypes.c_char_p, [_VP]),
     "shs_num_filters": (_I32, [_I32]),
     "shs_filters": (_I32, [_VP, _VP, _VP]),
     "shs_datacost": (_I32, [_VP, _VP, ctypes.POINTER(ctypes.c_float), ctypes.c_float, _VP, _VP]),
@@ -228,6 +229,10 @@ class Plan:
 
     def state_bytes(self) -> int:
         return int(lib().shs_state_bytes(self.handle))
+
+    def describe(self) -> str:
+        """shs_plan_describe: the plan's launch schedule."""
+        return lib().shs_plan_describe(self.handle).decode()
 
     def new_workspace(self):
         import torch

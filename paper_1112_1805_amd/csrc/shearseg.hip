@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -41,8 +43,10 @@ struct shs_plan {
   int* flist;          // filter ids, grouped by strip
   int2* strips_ana;    // per strip {first analysis item, items}
   int n_syn, n_ana, n_part;
+  int fc_syn;          // filters per synthesis work item
   long long nnz;       // stored filter values
   struct GraphCache* graphs;  // captured steady-state iterations of shs_solve
+  char schedule[256];  // chosen launch schedule (shs_plan_describe)
 };
 
 // Executable graphs of steady-state ADMM iterations, keyed by everything the captured
@@ -451,9 +455,8 @@ constexpr int kGenericMaxN = 1024;   // largest image side of the mixed-radix pa
 
 // Stage list of a mixed-radix transform of length L (radices 16, 8, 4, 2, 9, 3 and the
 // primes 5..23); false if L has a larger prime factor.
-bool make_fft_plan(int L, FftPlan& pl) {
-  pl = FftPlan{};
-  pl.L = L;
+// Default stage list of length L: empty if L has a prime factor above 23.
+std::vector<int> fft_factors(int L) {
   int m = L;
   std::vector<int> rs;
   for (int pr : {23, 19, 17, 13, 11, 7, 5}) while (m % pr == 0) { rs.push_back(pr); m /= pr; }
@@ -461,7 +464,17 @@ bool make_fft_plan(int L, FftPlan& pl) {
   while (m % 3 == 0) { rs.push_back(3); m /= 3; }
   while (m % 16 == 0) { rs.insert(rs.begin(), 16); m /= 16; }
   if (m == 2 || m == 4 || m == 8) { rs.insert(rs.begin(), m); m = 1; }
-  if (m != 1 || int(rs.size()) > kMaxStages) return false;
+  if (m != 1) rs.clear();
+  return rs;
+}
+
+// Plan of the stages `rs` (in this order; their product is L).
+bool fft_plan_from(int L, const std::vector<int>& rs, FftPlan& pl) {
+  pl = FftPlan{};
+  pl.L = L;
+  long long prod = 1;
+  for (int r : rs) prod *= r;
+  if (rs.empty() || prod != L || int(rs.size()) > kMaxStages) return false;
   pl.ns = int(rs.size());
   int ns = 1;
   for (int i = 0; i < pl.ns; ++i) {
@@ -476,6 +489,8 @@ bool make_fft_plan(int L, FftPlan& pl) {
   }
   return true;
 }
+
+bool make_fft_plan(int L, FftPlan& pl) { return fft_plan_from(L, fft_factors(L), pl); }
 
 bool get_ops_pow2(int n, Ops& o);
 
@@ -743,7 +758,14 @@ void build_items(const std::vector<std::vector<int>>& per_strip, const std::vect
   if (nparts) *nparts = slot;
 }
 
-shs_status build_pruned_layout(shs_plan* p) {
+// Filters meeting each strip (grouped by strip in flist), kept for re-cutting the synthesis
+// work items while the plan is tuned.
+struct StripLists {
+  std::vector<std::vector<int>> per_strip;
+  std::vector<int> strip_off;
+};
+
+shs_status build_pruned_layout(shs_plan* p, StripLists* keep) {
   const int n = p->n, half = p->M + 1, eta = p->eta, W = p->W;
   // 1. column windows of every filter
   int2* dwin = nullptr;
@@ -795,6 +817,11 @@ shs_status build_pruned_layout(shs_plan* p) {
   build_items(per_strip, strip_off, fc_ana, true, iana, &strips, &p->n_part);
   p->n_syn = int(isyn.size());
   p->n_ana = int(iana.size());
+  p->fc_syn = fc_syn;
+  if (keep) {
+    keep->per_strip = per_strip;
+    keep->strip_off = strip_off;
+  }
   shs_status st;
   if ((st = upload(&p->pwin, pwin)) != SHS_OK) return st;
   if ((st = upload(&p->tcol, tcol)) != SHS_OK) return st;
@@ -1176,6 +1203,252 @@ void launch_batch_iter(const BatchIter& iter, char* dbase, hipStream_t s) {
 }
 }  // namespace
 
+// ---------------------------------------------------------------- schedule tuning
+// Mixed-radix plans pick their launch schedule by timing candidates on their own kernels
+// at plan creation: rows per wave of the row pass, the stage order of the row FFT, the
+// stage order of the column FFT, and the filters per synthesis work item.  Rows per wave
+// and the synthesis item size leave every result bit-identical; the stage order changes the
+// FFT's rounding (results stay within the parity bounds, and are fixed for a given
+// schedule).  The choice is cached per (arch, N, J, q, store) for the process, and in the
+// file named by SHEARSEG_TUNE_CACHE when set (one line per key); SHEARSEG_TUNE=0 keeps the
+// default schedule.
+struct TuneCfg {
+  int rw = 1, fc_syn = 1;
+  std::vector<int> prow, pcol;
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<std::string, TuneCfg>> g_tune;   // process cache
+bool g_tune_loaded = false;
+
+std::string join_radices(const std::vector<int>& v, char sep) {
+  std::string out;
+  for (size_t i = 0; i < v.size(); ++i) out += (i ? std::string(1, sep) : std::string()) + std::to_string(v[i]);
+  return out;
+}
+std::vector<int> split_radices(const std::string& t) {
+  std::vector<int> v;
+  size_t i = 0;
+  while (i < t.size()) {
+    size_t j = t.find(',', i);
+    if (j == std::string::npos) j = t.size();
+    v.push_back(std::atoi(t.substr(i, j - i).c_str()));
+    i = j + 1;
+  }
+  return v;
+}
+
+void tune_cache_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("SHEARSEG_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char key[128], prow[128], pcol[128];
+  int rw, fc;
+  while (std::fscanf(f, "%127s %d %d %127s %127s", key, &rw, &fc, prow, pcol) == 5) {
+    TuneCfg c;
+    c.rw = rw;
+    c.fc_syn = fc;
+    c.prow = split_radices(prow);
+    c.pcol = split_radices(pcol);
+    g_tune.emplace_back(key, c);
+  }
+  std::fclose(f);
+}
+void tune_cache_store(const std::string& key, const TuneCfg& c) {
+  g_tune.emplace_back(key, c);
+  const char* path = std::getenv("SHEARSEG_TUNE_CACHE");
+  if (!path || !*path) return;
+  if (FILE* f = std::fopen(path, "a")) {
+    std::fprintf(f, "%s %d %d %s %s\n", key.c_str(), c.rw, c.fc_syn, join_radices(c.prow, ',').c_str(),
+                 join_radices(c.pcol, ',').c_str());
+    std::fclose(f);
+  }
+}
+
+// Stage orders worth timing: the default, reversed, radix 16 as 4 x 4, powers of two last.
+std::vector<std::vector<int>> order_candidates(const std::vector<int>& d) {
+  std::vector<std::vector<int>> out{d};
+  auto add = [&](const std::vector<int>& v) {
+    if (int(v.size()) <= kMaxStages && std::find(out.begin(), out.end(), v) == out.end()) out.push_back(v);
+  };
+  add(std::vector<int>(d.rbegin(), d.rend()));
+  std::vector<int> split;
+  for (int r : d) {
+    if (r == 16) { split.push_back(4); split.push_back(4); }
+    else split.push_back(r);
+  }
+  add(split);
+  std::vector<int> odd_first;
+  for (int r : d) if (r & 1) odd_first.push_back(r);
+  for (int r : d) if (!(r & 1)) odd_first.push_back(r);
+  add(odd_first);
+  return out;
+}
+
+// Installs a schedule in the plan: FFT plans and their twiddle tables, rows per wave, and
+// the synthesis work items.
+shs_status apply_schedule(shs_plan* p, const TuneCfg& c, const StripLists& sl) {
+  FftPlan pr, pc;
+  if (!fft_plan_from(p->M, c.prow, pr) || !fft_plan_from(p->n, c.pcol, pc)) return fail(SHS_E_DEVICE, "bad schedule");
+  const int n = p->n;
+  std::vector<float2> tw(n);
+  for (int m = 0; m < n; ++m) {
+    const double a = -2.0 * M_PI * double(m) / double(n);
+    tw[m] = make_float2(float(std::cos(a)), float(std::sin(a)));
+  }
+  std::vector<float2> tabs(size_t(n) / 2 + n);
+  fill_stage_tw_g(pr, tw, n, tabs.data());
+  fill_stage_tw_g(pc, tw, n, tabs.data() + n / 2);
+  HIPCHK(hipMemcpy(p->tw + n, tabs.data(), tabs.size() * sizeof(float2), hipMemcpyHostToDevice));
+  p->prow = pr;
+  p->pcol = pc;
+  p->rw = c.rw;
+  p->rpb = 4 * c.rw;
+  if (c.fc_syn != p->fc_syn) {
+    std::vector<int4> isyn;
+    build_items(sl.per_strip, sl.strip_off, c.fc_syn, false, isyn, nullptr, nullptr);
+    int4* d = nullptr;
+    const shs_status st = upload(&d, isyn);
+    if (st != SHS_OK) return st;
+    (void)hipFree(p->items_syn);
+    p->items_syn = d;
+    p->n_syn = int(isyn.size());
+    p->fc_syn = c.fc_syn;
+  }
+  return SHS_OK;
+}
+
+shs_status tune_schedule(shs_plan* p, const StripLists& sl) {
+  hipDeviceProp_t prop{};
+  HIPCHK(hipGetDeviceProperties(&prop, p->device));
+  const std::string key = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':')) +
+                          "/n" + std::to_string(p->n) + "/J" + std::to_string(p->J) + "/q" + std::to_string(p->q) +
+                          "/s" + std::to_string(p->store);
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_cache_load();
+  TuneCfg base;
+  base.rw = p->rw;
+  base.fc_syn = p->fc_syn;
+  base.prow = fft_factors(p->M);
+  base.pcol = fft_factors(p->n);
+  for (auto& e : g_tune)
+    if (e.first == key) {
+      const shs_status st = apply_schedule(p, e.second, sl);
+      if (st == SHS_OK)
+        std::snprintf(p->schedule, sizeof(p->schedule), "%s: rows/wave %d, row radices %s, column radices %s, "
+                      "synthesis run %d (cached)", key.c_str(), p->rw, join_radices(e.second.prow, 'x').c_str(),
+                      join_radices(e.second.pcol, 'x').c_str(), p->fc_syn);
+      return st;
+    }
+  const char* off = std::getenv("SHEARSEG_TUNE");
+  if (off && std::string(off) == "0") {
+    std::snprintf(p->schedule, sizeof(p->schedule), "%s: rows/wave %d, row radices %s, column radices %s, "
+                  "synthesis run %d (default)", key.c_str(), p->rw, join_radices(base.prow, 'x').c_str(),
+                  join_radices(base.pcol, 'x').c_str(), p->fc_syn);
+    return SHS_OK;
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  // a workspace for one label's channels, sized for the smallest rows per block
+  const int rw0 = p->rw, rpb0 = p->rpb;
+  p->rw = 1;
+  p->rpb = 4;
+  const Layout L = make_layout(p);
+  p->rw = rw0;
+  p->rpb = rpb0;
+  void* ws = nullptr;
+  if (hipMalloc(&ws, L.total) != hipSuccess) return fail(SHS_E_NOMEM, "tuning workspace");
+  struct Free {
+    void* w;
+    ~Free() { (void)hipFree(w); }
+  } fr{ws};
+  HIPCHK(hipMemset(ws, 0, L.total));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  struct FreeEv {
+    hipEvent_t a, b;
+    ~FreeEv() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } fe{e0, e1};
+  CaptureScope cs;   // no profiling events while tuning
+  auto time_ms = [&](auto&& launch) -> float {
+    launch();
+    (void)hipEventRecord(e0, 0);
+    for (int r = 0; r < 3; ++r) launch();
+    (void)hipEventRecord(e1, 0);
+    float ms = 1e30f;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return 1e30f;
+    return ms;
+  };
+  TuneCfg best = base;
+  int tried = 0;
+  // row pass: rows per wave x row stage order (one label's channels, state update on)
+  float best_row = 1e30f;
+  for (int rw : {1, 2, 4}) {
+    if (rw == 4 && !(p->n % 16 == 0 && p->M <= 192)) continue;
+    if (rw == 2 && p->M > 384) continue;
+    for (const auto& ord : order_candidates(base.prow)) {
+      TuneCfg c = best;
+      c.rw = rw;
+      c.prow = ord;
+      shs_status st = apply_schedule(p, c, sl);
+      if (st != SHS_OK) return st;
+      Ctx cx;
+      if ((st = make_ctx(p, ws, L.total, nullptr, cx)) != SHS_OK) return st;
+      RowParams rp{};
+      rp.spec_in = cx.at<float2>(cx.L.t1);
+      rp.lin = pruned_layout(p);
+      rp.spec_out = cx.at<float2>(cx.L.t2);
+      rp.lout = pruned_layout(p);
+      rp.g = cx.ws + cx.L.g;
+      rp.emit = 1;
+      const float ms = time_ms([&] { run_row(cx, ROW_SOLVE, p->store, false, rp, p->eta); });
+      ++tried;
+      if (ms < best_row) { best_row = ms; best.rw = rw; best.prow = ord; }
+    }
+  }
+  // column passes: column stage order x synthesis run length (one label)
+  float best_col = 1e30f;
+  std::vector<int> fcs;
+  for (int fc : {1, 2, 4, 8, 16}) if (fc <= kItemMax) fcs.push_back(fc);
+  for (const auto& ord : order_candidates(base.pcol)) {
+    for (int fc : fcs) {
+      TuneCfg c = best;
+      c.pcol = ord;
+      c.fc_syn = fc;
+      shs_status st = apply_schedule(p, c, sl);
+      if (st != SHS_OK) return st;
+      Ctx cx;
+      if ((st = make_ctx(p, ws, L.total, nullptr, cx)) != SHS_OK) return st;
+      ColParams cp = col_params(cx, 1);
+      const float ms = time_ms([&] {
+        ColParams a = cp;
+        a.in = cx.at<float2>(cx.L.v);
+        a.out = cx.at<float2>(cx.L.t1);
+        a.items = p->items_syn;
+        run_col(cx, COL_SYN, a, p->n_syn, 1);
+        ColParams b = cp;
+        b.in = cx.at<float2>(cx.L.t2);
+        b.out = cx.at<float2>(cx.L.z);
+        b.items = p->items_ana;
+        run_col(cx, COL_ANA, b, p->n_ana, 1);
+      });
+      ++tried;
+      if (ms < best_col) { best_col = ms; best.pcol = ord; best.fc_syn = fc; }
+    }
+  }
+  LAUNCHCHK("schedule tuning");
+  shs_status st = apply_schedule(p, best, sl);
+  if (st != SHS_OK) return st;
+  tune_cache_store(key, best);
+  const double tms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  std::snprintf(p->schedule, sizeof(p->schedule), "%s: rows/wave %d, row radices %s, column radices %s, synthesis "
+                "run %d (tuned: %d candidates, %.0f ms)", key.c_str(), p->rw, join_radices(best.prow, 'x').c_str(),
+                join_radices(best.pcol, 'x').c_str(), p->fc_syn, tried, tms);
+  return SHS_OK;
+}
+
 // ---------------------------------------------------------------- graph replay
 constexpr int kGraphIters = 8;   // ADMM iterations per captured graph
 
@@ -1457,11 +1730,16 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
       return fail(SHS_E_DEVICE, "cannot reserve LDS for the mixed-radix column passes");
     }
   }
-  const shs_status st = build_pruned_layout(p);
+  StripLists sl;
+  shs_status st = build_pruned_layout(p, &sl);
+  if (st == SHS_OK && p->generic) st = tune_schedule(p, sl);
   if (st != SHS_OK) {
     free_plan(p);
     return st;
   }
+  if (!p->generic)
+    std::snprintf(p->schedule, sizeof(p->schedule), "n%d: power-of-two path, row FFT %d-point (compile-time "
+                  "radices), column strips of %d, synthesis run %d", n, p->M, p->W, p->fc_syn);
   *out = p;
   return SHS_OK;
 }
@@ -1475,6 +1753,8 @@ shs_status shs_plan_destroy(shs_plan* p) {
 
 size_t shs_workspace_bytes(const shs_plan* p) { return p ? make_layout(p).total : 0; }
 size_t shs_state_bytes(const shs_plan* p) { return p ? make_layout(p).state_end : 0; }
+
+const char* shs_plan_describe(const shs_plan* p) { return p ? p->schedule : ""; }
 
 shs_status shs_filters(const shs_plan* p, float* d_psi, void* stream) {
   if (!p || !d_psi) return fail(SHS_E_INVALID, "null argument");

@@ -26,7 +26,7 @@ def test_header_declares_expected_entry_points():
                  "shs_num_filters", "shs_filters", "shs_datacost", "shs_shearlet_forward",
                  "shs_shearlet_adjoint", "shs_shearlet_denoise", "shs_solve", "shs_solve_pd", "shs_solve_tv", "shs_nl_graph", "shs_solve_nl", "shs_energy", "shs_status_str", "shs_last_error",
                  "shs_batch_create", "shs_batch_destroy", "shs_batch_workspace_bytes", "shs_solve_batch",
-                 "shs_profile_begin", "shs_profile_begin_classes", "shs_profile_end", "shs_solve_noalloc"]:
+                 "shs_profile_begin", "shs_profile_begin_classes", "shs_profile_end", "shs_solve_noalloc", "shs_plan_describe"]:
         assert name in syms
 
 
@@ -52,6 +52,7 @@ def test_pure_host_entry_points():
     assert L.shs_workspace_bytes(None) == 0 and L.shs_state_bytes(None) == 0
     assert L.shs_status_str(pkg.SHS_E_WORKSPACE) == b"workspace too small or missing"
     assert L.shs_plan_destroy(None) == pkg.SHS_OK
+    assert L.shs_plan_describe(None) == b""
 
 
 def test_profile_class_selection_is_validated():

@@ -820,6 +820,29 @@ def test_mixed_radix_solves(n, q, J, C, iters):
     assert np.max(np.abs(h[:, 2] - r.r_combined) / r.r_combined) < 1e-3
 
 
+def test_schedule_tuning_cached_and_described():
+    # mixed-radix plans time their schedule candidates at creation; a second plan of the same
+    # shape reuses the choice (process cache), so both give the same bits
+    pkg = _pkg()
+    w = make_small(352, 2, 3, seed=61, lam=0.1, iters=6)
+    a = pkg.Plan(352, 1, 2, 3)
+    b = pkg.Plan(352, 1, 2, 3)
+    da, db = a.describe(), b.describe()
+    print(da)
+    assert "rows/wave" in da and ("tuned" in da or "cached" in da)
+    assert "cached" in db and da.split(" (")[0] == db.split(" (")[0]
+    assert "power-of-two" in pkg.Plan(256, 1, 2, 2).describe()
+    outs = []
+    for plan in (a, b):
+        s = torch.empty((2, 352, 352), device="cuda:0")
+        plan.datacost(dev_t(w.img), w.codebook, s)
+        u = torch.empty_like(s)
+        plan.solve(s, plan.new_workspace(), w.lam, w.gamma, w.iters, u=u)
+        torch.cuda.synchronize()
+        outs.append(u.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_unsupported_sizes_rejected():
     pkg = _pkg()
     for n in (100, 62, 1056, 2 * 29 * 8):
