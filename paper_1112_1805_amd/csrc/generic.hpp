@@ -71,7 +71,10 @@ __device__ __forceinline__ void dft_any(cpx (&a)[R]) {
 // sw[i Ns + k - 1] (1 <= i < R, k < Ns) for the stage of stride Ns and radix R; the stages'
 // ranges [Ns - 1, Ns R - 1) tile [0, L - 1), and consecutive butterflies read consecutive
 // entries.
-template <int R, bool INV, int W>
+// TWL: sw is a copy of the table in LDS and every twiddle power is read from it (no
+// products, no vector-memory loads); otherwise the power-of-two exponents are loaded from
+// global memory and the others formed by products.
+template <int R, bool INV, int W, bool TWL>
 __device__ __forceinline__ void gstage(const float2* __restrict__ src, float2* __restrict__ dst, int L, int Ns,
                                        unsigned mag, int sh, int nthr, int tid, const float2* __restrict__ sw) {
   static_assert((W & (W - 1)) == 0, "strip width is a power of two");
@@ -88,15 +91,21 @@ __device__ __forceinline__ void gstage(const float2* __restrict__ src, float2* _
       // z^i with z = W_{Ns R}^k: the power-of-two exponents are loaded, the others are
       // products of two of them (fewer loads through the vector-memory data path)
       cpx w[R];
-      static_for<R>([&](auto i) {
-        if constexpr (i > 0 && (i & (i - 1)) == 0) w[i] = ld(sw + (i * Ns + k - 1));
-      });
-      static_for<R>([&](auto i) {
-        if constexpr (i > 0 && (i & (i - 1)) != 0) {
-          constexpr int hi = 1 << (31 - __builtin_clz(unsigned(i)));
-          w[i] = cmul(w[hi], w[i - hi]);
-        }
-      });
+      if constexpr (TWL) {
+        static_for<R>([&](auto i) {
+          if constexpr (i > 0) w[i] = ld(sw + (i * Ns + k - 1));
+        });
+      } else {
+        static_for<R>([&](auto i) {
+          if constexpr (i > 0 && (i & (i - 1)) == 0) w[i] = ld(sw + (i * Ns + k - 1));
+        });
+        static_for<R>([&](auto i) {
+          if constexpr (i > 0 && (i & (i - 1)) != 0) {
+            constexpr int hi = 1 << (31 - __builtin_clz(unsigned(i)));
+            w[i] = cmul(w[hi], w[i - hi]);
+          }
+        });
+      }
       static_for<R - 1>([&](auto i1) {
         constexpr int i = i1 + 1;
         a[i] = INV ? cmulc(a[i], w[i]) : cmul(a[i], w[i]);
@@ -109,7 +118,7 @@ __device__ __forceinline__ void gstage(const float2* __restrict__ src, float2* _
 }
 
 // Full transform: data in b0 (natural order) -> result (natural order) in the returned buffer.
-template <bool INV, int SK, int W>
+template <bool INV, int SK, int W, bool TWL = false>
 __device__ __forceinline__ float2* gfft(float2* b0, float2* b1, const FftPlan& pl, int nthr, int tid, const float2* __restrict__ sw) {
   float2* src = b0;
   float2* dst = b1;
@@ -119,19 +128,19 @@ __device__ __forceinline__ float2* gfft(float2* b0, float2* b1, const FftPlan& p
     const unsigned mg = pl.mag[s];
     const int sh = pl.sh[s];
     switch (r) {
-      case 2: gstage<2, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
-      case 3: gstage<3, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
-      case 4: gstage<4, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
-      case 5: gstage<5, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
-      case 7: gstage<7, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
-      case 8: gstage<8, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
-      case 9: gstage<9, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
-      case 11: gstage<11, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
-      case 13: gstage<13, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
-      case 16: gstage<16, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
-      case 17: gstage<17, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
-      case 19: gstage<19, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
-      case 23: gstage<23, INV, W>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 2: gstage<2, INV, W, TWL>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 3: gstage<3, INV, W, TWL>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 4: gstage<4, INV, W, TWL>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 5: gstage<5, INV, W, TWL>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 7: gstage<7, INV, W, TWL>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 8: gstage<8, INV, W, TWL>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 9: gstage<9, INV, W, TWL>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 11: gstage<11, INV, W, TWL>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 13: gstage<13, INV, W, TWL>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 16: gstage<16, INV, W, TWL>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 17: gstage<17, INV, W, TWL>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 19: gstage<19, INV, W, TWL>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
+      case 23: gstage<23, INV, W, TWL>(src, dst, pl.L, Ns, mg, sh, nthr, tid, sw); break;
       default: break;
     }
     fft_sync<SK>();
@@ -157,6 +166,17 @@ struct GenParams {
 __device__ __forceinline__ const float2* row_sw_g(const float2* tw, int n) { return tw + n; }
 __device__ __forceinline__ const float2* col_sw_g(const float2* tw, int n) { return tw + n + n / 2; }
 
+// The kernels below keep their twiddles in LDS, at the start of the dynamic shared memory
+// (loaded once per block): the mixed-radix stages read one table entry per twiddle, where
+// loads from global memory would compete with the data for the vector-memory path.
+//   row pass:     exp(-2 pi i k / N) for k <= N/2, then the row FFT's stage table
+//   column pass:  the column FFT's stage table (N - 1 entries, padded to N)
+__host__ __device__ constexpr int row_tab_len(int n) { return n; }       // (N/2 + 1) + (N/2 - 1)
+__host__ __device__ constexpr int col_tab_len(int n) { return n; }
+__device__ __forceinline__ void load_table(float2* dst, const float2* __restrict__ src, int len) {
+  for (int e = threadIdx.x; e < len; e += blockDim.x) dst[e] = src[e];
+}
+
 // ---------------------------------------------------------------- generic row pass
 // Same modes and data contract as k_row.  Each wave transforms RW rows at once, stored
 // interleaved in LDS (bin k of row c at k * RW + c, two half-length complex buffers per
@@ -177,10 +197,15 @@ __device__ __forceinline__ void row_g_body(const RowParams& p, const GenParams& 
   const int row0 = (bid.x * 4 + wave) * RW;
   const int ch = bid.y;
   const int j = ch % p.eta;
-  float2* b0 = gsm + wave * 2 * M * RW;
+  float2* ltw = gsm;                 // exp(-2 pi i k / N), k <= M
+  float2* lsw = gsm + M + 1;         // row FFT stage table
+  load_table(ltw, p.tw, M + 1);
+  load_table(lsw, row_sw_g(p.tw, n), M - 1);
+  float2* b0 = gsm + row_tab_len(n) + wave * 2 * M * RW;
   float2* b1 = b0 + M * RW;
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   float2* res = b0;
+  __syncthreads();
 
   if constexpr (MODE == ROW_SOLVE || MODE == ROW_C2R || MODE == ROW_ENERGY || MODE == ROW_SHRINK || MODE == ROW_PD) {
     int cb, pitch;
@@ -194,12 +219,12 @@ __device__ __forceinline__ void row_g_body(const RowParams& p, const GenParams& 
         const cpx xp = B.load(tix_g(k - cb, row, n));
         const cpx xm = conj(B.load(tix_g(M - k - cb, row, n)));
         const cpx s = xp + xm, d = xp - xm;
-        const cpx w = conj(ld(p.tw + k));
+        const cpx w = conj(ld(ltw + k));
         st(b0 + k * RW + c, s + mul_i(cmul(d, w)));
       }
     }
     fft_sync<SYNC_WAVE>();
-    res = gfft<true, SYNC_WAVE, RW>(b0, b1, gp.prow, 64, lane, row_sw_g(p.tw, n));
+    res = gfft<true, SYNC_WAVE, RW, true>(b0, b1, gp.prow, 64, lane, lsw);
   }
   if constexpr (MODE == ROW_C2R) {
     for (int c = 0; c < RW; ++c) {
@@ -280,7 +305,7 @@ __device__ __forceinline__ void row_g_body(const RowParams& p, const GenParams& 
     if (emit) {
       fft_sync<SYNC_WAVE>();
       float2* other = res == b0 ? b1 : b0;
-      float2* Y = gfft<false, SYNC_WAVE, RW>(res, other, gp.prow, 64, lane, row_sw_g(p.tw, n));
+      float2* Y = gfft<false, SYNC_WAVE, RW, true>(res, other, gp.prow, 64, lane, lsw);
       int cb, pitch;
       long long off;
       plane_geom(p.lout, ch % p.lout.nf, cb, pitch, off);
@@ -292,7 +317,7 @@ __device__ __forceinline__ void row_g_body(const RowParams& p, const GenParams& 
           const cpx yk = ld(Y + (k == M ? 0 : k) * RW + c);
           const cpx ym = conj(ld(Y + (k == 0 ? 0 : M - k) * RW + c));
           const cpx s = yk + ym, d = yk - ym;
-          const cpx w = ld(p.tw + k);
+          const cpx w = ld(ltw + k);
           B.store(tix_g(k - cb, row, n), (s - mul_i(cmul(d, w))) * 0.5f);
         }
       }
@@ -337,12 +362,14 @@ __device__ __forceinline__ void stage_item_g(const ColParams& p, int4 it, int M,
 __device__ __forceinline__ void colg_fwd_body(const ColParams& p, const GenParams& gp, BlockId bid) {
   extern __shared__ float2 gsm[];
   const int n = gp.n, E = n * kGW;
-  float2* b0 = gsm;
-  float2* b1 = gsm + E;
+  float2* lsw = gsm;
+  float2* b0 = gsm + col_tab_len(n);
+  float2* b1 = b0 + E;
+  load_table(lsw, col_sw_g(p.tw, n), n - 1);
   const long long strip = bid.y * (long long)n * p.P + (long long)bid.x * E;
   for (int e = threadIdx.x; e < E; e += 256) b0[e] = p.in[strip + e];
   __syncthreads();
-  float2* r = gfft<false, SYNC_BLOCK, kGW>(b0, b1, gp.pcol, 256, threadIdx.x, col_sw_g(p.tw, gp.n));
+  float2* r = gfft<false, SYNC_BLOCK, kGW, true>(b0, b1, gp.pcol, 256, threadIdx.x, lsw);
   const int M = n / 2;
   for (int e = threadIdx.x; e < E; e += 256)
     if (bid.x * kGW + (e % kGW) <= M) p.out[strip + e] = r[e];
@@ -355,12 +382,14 @@ __global__ __launch_bounds__(256) void k_colg_fwd(ColParams p, GenParams gp) {
 __device__ __forceinline__ void colg_syn_body(const ColParams& p, const GenParams& gp, BlockId bid) {
   extern __shared__ float2 gsm[];
   const int n = gp.n, E = n * kGW, M = n / 2;
-  float2* bu = gsm;
-  float2* b0 = gsm + E;
-  float2* b1 = gsm + 2 * E;
+  float2* lsw = gsm;
+  float2* bu = gsm + col_tab_len(n);
+  float2* b0 = bu + E;
+  float2* b1 = bu + 2 * E;
   __shared__ ItemStage<kGW> stg;
   const int4 it = p.items[bid.x];
   const int l = bid.y;
+  load_table(lsw, col_sw_g(p.tw, n), n - 1);
   stage_item_g(p, it, M, stg);
   const float2* U = p.in + l * (long long)n * p.P + (long long)it.x * E;
   for (int e = threadIdx.x; e < E; e += 256) bu[e] = U[e];
@@ -371,7 +400,7 @@ __device__ __forceinline__ void colg_syn_body(const ColParams& p, const GenParam
       b0[e] = make_float2(bu[e].x * f * p.inv_n2, bu[e].y * f * p.inv_n2);
     }
     __syncthreads();
-    float2* r = gfft<true, SYNC_BLOCK, kGW>(b0, b1, gp.pcol, 256, threadIdx.x, col_sw_g(p.tw, gp.n));
+    float2* r = gfft<true, SYNC_BLOCK, kGW, true>(b0, b1, gp.pcol, 256, threadIdx.x, lsw);
     const int4 geo = stg.geo[i];
     float2* o = p.out + l * p.tl.ls + geo_off(geo) + (long long)(it.x - geo.x / kGW) * E;
     for (int e = threadIdx.x; e < E; e += 256)
@@ -384,11 +413,12 @@ __global__ __launch_bounds__(256) void k_colg_syn(ColParams p, GenParams gp) {
   colg_syn_body(p, gp, own_block());
 }
 
-__device__ __forceinline__ void colg_finish(const ColParams& p, const GenParams& gp, float2* acc, float2* b1, int strip, int l) {
+__device__ __forceinline__ void colg_finish(const ColParams& p, const GenParams& gp, const float2* lsw, float2* acc,
+                                            float2* b1, int strip, int l) {
   const int n = gp.n, E = n * kGW, M = n / 2;
   for (int e = threadIdx.x; e < E; e += 256) acc[e] = make_float2(acc[e].x * p.inv_n2, acc[e].y * p.inv_n2);
   __syncthreads();
-  float2* r = gfft<true, SYNC_BLOCK, kGW>(acc, b1, gp.pcol, 256, threadIdx.x, col_sw_g(p.tw, gp.n));
+  float2* r = gfft<true, SYNC_BLOCK, kGW, true>(acc, b1, gp.pcol, 256, threadIdx.x, lsw);
   float2* o = p.out + l * (long long)n * p.P + (long long)strip * E;
   for (int e = threadIdx.x; e < E; e += 256)
     if (strip * kGW + (e % kGW) <= M) o[e] = r[e];
@@ -397,12 +427,14 @@ __device__ __forceinline__ void colg_finish(const ColParams& p, const GenParams&
 __device__ __forceinline__ void colg_ana_body(const ColParams& p, const GenParams& gp, BlockId bid) {
   extern __shared__ float2 gsm[];
   const int n = gp.n, E = n * kGW, M = n / 2;
-  float2* ba = gsm;
-  float2* b0 = gsm + E;
-  float2* b1 = gsm + 2 * E;
+  float2* lsw = gsm;
+  float2* ba = gsm + col_tab_len(n);
+  float2* b0 = ba + E;
+  float2* b1 = ba + 2 * E;
   __shared__ ItemStage<kGW> stg;
   const int4 it = p.items[bid.x];
   const int l = bid.y;
+  load_table(lsw, col_sw_g(p.tw, n), n - 1);
   stage_item_g(p, it, M, stg);
   for (int e = threadIdx.x; e < E; e += 256) ba[e] = make_float2(0.f, 0.f);
   __syncthreads();
@@ -414,7 +446,7 @@ __device__ __forceinline__ void colg_ana_body(const ColParams& p, const GenParam
       b0[e] = k1 <= M ? in[e] : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    float2* r = gfft<false, SYNC_BLOCK, kGW>(b0, b1, gp.pcol, 256, threadIdx.x, col_sw_g(p.tw, gp.n));
+    float2* r = gfft<false, SYNC_BLOCK, kGW, true>(b0, b1, gp.pcol, 256, threadIdx.x, lsw);
     for (int e = threadIdx.x; e < E; e += 256) {
       const float f = psi_at_rt(p, stg.win[i][e % kGW], e / kGW, n);   // zero window past N/2
       ba[e] = make_float2(ba[e].x + r[e].x * f, ba[e].y + r[e].y * f);
@@ -422,7 +454,7 @@ __device__ __forceinline__ void colg_ana_body(const ColParams& p, const GenParam
     __syncthreads();
   }
   if (it.w < 0) {
-    colg_finish(p, gp, ba, b1, it.x, l);
+    colg_finish(p, gp, lsw, ba, b1, it.x, l);
   } else {
     float2* o = p.part + ((long long)it.w * p.labels + l) * E;
     for (int e = threadIdx.x; e < E; e += 256) o[e] = ba[e];
@@ -438,16 +470,18 @@ __device__ __forceinline__ void colg_final_body(const ColParams& p, const GenPar
   const int n = gp.n, E = n * kGW;
   const int2 si = p.strips[bid.x];
   if (si.y <= 1) return;
-  float2* ba = gsm;
-  float2* b1 = gsm + E;
+  float2* lsw = gsm;
+  float2* ba = gsm + col_tab_len(n);
+  float2* b1 = ba + E;
   const int l = bid.y;
+  load_table(lsw, col_sw_g(p.tw, n), n - 1);
   for (int e = threadIdx.x; e < E; e += 256) ba[e] = make_float2(0.f, 0.f);
   for (int i = 0; i < si.y; ++i) {
     const float2* in = p.part + ((long long)p.items[si.x + i].w * p.labels + l) * E;
     for (int e = threadIdx.x; e < E; e += 256) ba[e] = make_float2(ba[e].x + in[e].x, ba[e].y + in[e].y);
   }
   __syncthreads();
-  colg_finish(p, gp, ba, b1, bid.x, l);
+  colg_finish(p, gp, lsw, ba, b1, bid.x, l);
 }
 
 __global__ __launch_bounds__(256) void k_colg_final(ColParams p, GenParams gp) {

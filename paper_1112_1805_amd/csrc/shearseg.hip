@@ -373,7 +373,7 @@ struct GenPipe {
   static void row_t(const shs_plan* p, const RowParams& rp, int channels, hipStream_t s) {
     // 4 waves per block, p->rw rows per wave
     const dim3 grid(p->n / p->rpb, channels);
-    const size_t lds = size_t(4) * 2 * p->M * p->rw * sizeof(float2);
+    const size_t lds = (size_t(4) * 2 * p->M * p->rw + row_tab_len(p->n)) * sizeof(float2);
     if (g_rec) {
       LaunchRec* r = nullptr;
       switch (p->rw) {
@@ -418,13 +418,14 @@ struct GenPipe {
   static void col(const shs_plan* p, int kind, const ColParams& cp, int nblocks, int labels, hipStream_t s) {
     const dim3 grid(nblocks, labels), block(256);
     const size_t e = size_t(p->n) * kGW * sizeof(float2);
+    const size_t t = size_t(col_tab_len(p->n)) * sizeof(float2);
     if (g_rec) {
       LaunchRec* r = nullptr;
       switch (kind) {
-        case 0: r = &rec_add(RK_COL, &kg_colg_fwd, 256, nblocks, labels, 2 * e); break;
-        case 1: r = &rec_add(RK_COL, &kg_colg_syn, 256, nblocks, labels, 3 * e); break;
-        case 2: r = &rec_add(RK_COL, &kg_colg_ana, 256, nblocks, labels, 3 * e); break;
-        case 3: r = &rec_add(RK_COL, &kg_colg_final, 256, nblocks, labels, 2 * e); break;
+        case 0: r = &rec_add(RK_COL, &kg_colg_fwd, 256, nblocks, labels, t + 2 * e); break;
+        case 1: r = &rec_add(RK_COL, &kg_colg_syn, 256, nblocks, labels, t + 3 * e); break;
+        case 2: r = &rec_add(RK_COL, &kg_colg_ana, 256, nblocks, labels, t + 3 * e); break;
+        case 3: r = &rec_add(RK_COL, &kg_colg_final, 256, nblocks, labels, t + 2 * e); break;
       }
       if (r) {
         r->cp = cp;
@@ -433,10 +434,10 @@ struct GenPipe {
       return;
     }
     switch (kind) {
-      case 0: hipLaunchKernelGGL(k_colg_fwd, grid, block, 2 * e, s, cp, gp(p)); break;
-      case 1: hipLaunchKernelGGL(k_colg_syn, grid, block, 3 * e, s, cp, gp(p)); break;
-      case 2: hipLaunchKernelGGL(k_colg_ana, grid, block, 3 * e, s, cp, gp(p)); break;
-      case 3: hipLaunchKernelGGL(k_colg_final, grid, block, 2 * e, s, cp, gp(p)); break;
+      case 0: hipLaunchKernelGGL(k_colg_fwd, grid, block, t + 2 * e, s, cp, gp(p)); break;
+      case 1: hipLaunchKernelGGL(k_colg_syn, grid, block, t + 3 * e, s, cp, gp(p)); break;
+      case 2: hipLaunchKernelGGL(k_colg_ana, grid, block, t + 3 * e, s, cp, gp(p)); break;
+      case 3: hipLaunchKernelGGL(k_colg_final, grid, block, t + 2 * e, s, cp, gp(p)); break;
     }
   }
 };
@@ -1180,7 +1181,7 @@ void build_batch_iter(const std::vector<LaunchRec>& recs, std::vector<char>& are
 // takes its largest image's LDS, so only images of one occupancy share a launch).
 int batch_class(const shs_plan* p) {
   if (!p->generic) return p->n;
-  const int lds3 = 3 * p->n * kGW * int(sizeof(float2));
+  const int lds3 = (3 * p->n * kGW + col_tab_len(p->n)) * int(sizeof(float2));
   const int bpc = std::min(4, (160 * 1024) / lds3);
   return 100000 + p->rw * 10 + bpc;
 }
@@ -1661,7 +1662,8 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
   p->pcol = pcol;
   p->W = pow2 ? by_size<WOf>(n) : kGW;
   // generic rows: several rows per wave keep the lanes busy in stages with few butterflies;
-  // the two LDS buffers of a block (4 waves, 64 M rw bytes) stay at or below 48 KB
+  // the two LDS buffers of a block (4 waves, 64 M rw bytes) stay at or below 48 KB, beside
+  // the 8 N bytes of twiddle tables
   p->rw = pow2 ? 1 : (n % 16 == 0 && p->M <= 192) ? 4 : (p->M <= 384 ? 2 : 1);
   p->rpb = pow2 ? by_size<RpbOf>(n) : 4 * p->rw;
   p->NS = p->M / p->W + 1;
@@ -1704,10 +1706,11 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
     return fail(SHS_E_DEVICE, "filter generation failed");
   }
   if (p->generic) {
-    // generic column passes hold 3 strips of N x 4 bins in dynamic LDS (up to 96 KB); the
-    // cap is set for the largest supported N, so plans of any size can be created in any order
-    const int lds3 = 3 * kGenericMaxN * kGW * int(sizeof(float2));
-    const int lds2 = 2 * kGenericMaxN * kGW * int(sizeof(float2));
+    // generic column passes hold their twiddle table and 3 strips of N x 4 bins in dynamic
+    // LDS (up to 104 KB); the cap is set for the largest supported N, so plans of any size
+    // can be created in any order
+    const int lds3 = (3 * kGenericMaxN * kGW + col_tab_len(kGenericMaxN)) * int(sizeof(float2));
+    const int lds2 = (2 * kGenericMaxN * kGW + col_tab_len(kGenericMaxN)) * int(sizeof(float2));
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colg_syn), hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds3) != hipSuccess ||
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colg_ana), hipFuncAttributeMaxDynamicSharedMemorySize,
