@@ -105,6 +105,32 @@ template <> struct Store<ST_F16> {
 // x clipped to [-th, th] (th >= 0): one median-of-three instruction
 __device__ __forceinline__ float clip(float x, float th) { return __builtin_amdgcn_fmed3f(x, -th, th); }
 
+// 16 bytes of stored pairs (2 FP32 pairs or 4 16-bit pairs), moved with one vector access.
+template <class Pair>
+struct PairVec {
+  static constexpr int V = 16 / int(sizeof(Pair));
+  __device__ __forceinline__ static void load(const void* p, Pair (&out)[V]) {
+    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    const unsigned w[4] = {v.x, v.y, v.z, v.w};
+    if constexpr (V == 4) {
+      for (int i = 0; i < 4; ++i) out[i] = __builtin_bit_cast(Pair, w[i]);
+    } else {
+      for (int i = 0; i < 2; ++i) out[i] = make_float2(__uint_as_float(w[2 * i]), __uint_as_float(w[2 * i + 1]));
+    }
+  }
+  __device__ __forceinline__ static void store(void* p, const Pair (&in)[V]) {
+    uint4 v;
+    if constexpr (V == 4) {
+      v.x = __builtin_bit_cast(unsigned, in[0]); v.y = __builtin_bit_cast(unsigned, in[1]);
+      v.z = __builtin_bit_cast(unsigned, in[2]); v.w = __builtin_bit_cast(unsigned, in[3]);
+    } else {
+      v.x = __float_as_uint(in[0].x); v.y = __float_as_uint(in[0].y);
+      v.z = __float_as_uint(in[1].x); v.w = __float_as_uint(in[1].y);
+    }
+    *reinterpret_cast<uint4*>(p) = v;
+  }
+};
+
 // ---------------------------------------------------------------- FP64 block reduction
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -482,6 +508,8 @@ template <int N, int MODE, int ST, bool STATS>
 __device__ __forceinline__ void row_body(const RowParams& p, BlockId bid) {
   using G = RowGeom<N>;
   using S = Store<ST>;
+  using PV = PairVec<typename S::Pair>;
+  static_assert(G::R % PV::V == 0, "a thread's pairs fill whole 16-byte groups");
   __shared__ float2 lds[G::RPB * G::LROW];
   __shared__ float2 twl[G::TW_LDS];
   __shared__ double red[G::WAVES * 4];
@@ -498,9 +526,16 @@ __device__ __forceinline__ void row_body(const RowParams& p, BlockId bid) {
   typename S::Pair gv[G::R];
   if constexpr (MODE == ROW_SOLVE || MODE == ROW_PRIME || MODE == ROW_PD) {
     // The state does not depend on the inverse FFT below: load it first so its latency
-    // overlaps the FFT.
+    // overlaps the FFT.  A row of the state is stored in the order the row pass holds it:
+    // thread t's pairs r = V i .. V i + V - 1 (points 2p, 2p+1 of p = t + r T) are the 16
+    // bytes at pair offset (i T + t) V, so each of the R / V loads (and stores) of a wave is
+    // one contiguous run per row.  Only this pass reads or writes the state.
     gp = reinterpret_cast<typename S::T*>(p.g) + (long long)ch * N * N + (long long)row * N;
-    static_for<G::R>([&](auto r) { gv[r] = S::load_pair(gp + 2 * (t + r * G::T)); });
+    static_for<G::R / PV::V>([&](auto i) {
+      typename S::Pair v[PV::V];
+      PV::load(gp + 2 * PV::V * (i * G::T + t), v);
+      static_for<PV::V>([&](auto e) { gv[i * PV::V + e] = v[e]; });
+    });
   }
   // the block's twiddle table (pre/post factors, then the FFT stage table)
   for (int e = threadIdx.x; e < G::TW_LDS; e += G::THREADS)
@@ -536,8 +571,8 @@ __device__ __forceinline__ void row_body(const RowParams& p, BlockId bid) {
   }
   if constexpr (MODE == ROW_SOLVE || MODE == ROW_PRIME) {
     const float th = p.fw.thr[j];
+    typename S::Pair nv[PV::V];
     static_for<G::R>([&](auto r) {
-      const int k = t + r * G::T;
       float g0, g1;
       S::unpack(gv[r], g0, g1);
       const float b0 = clip(g0, th), b1 = clip(g1, th);
@@ -546,7 +581,8 @@ __device__ __forceinline__ void row_body(const RowParams& p, BlockId bid) {
         // g <- clip(g) + S_j u  (v = shrink(g), b_v = clip(g); Section 3 v- and b_v-updates)
         n0 = b0 + a[r].x;
         n1 = b1 + a[r].y;
-        S::store_pair(gp + 2 * k, S::round2(n0, n1));
+        nv[r % PV::V] = S::round2(n0, n1);
+        if constexpr (r % PV::V == PV::V - 1) PV::store(gp + 2 * PV::V * ((r / PV::V) * G::T + t), nv);
       }
       const float nb0 = clip(n0, th), nb1 = clip(n1, th);
       if constexpr (STATS && MODE == ROW_SOLVE) {
@@ -570,12 +606,14 @@ __device__ __forceinline__ void row_body(const RowParams& p, BlockId bid) {
   if constexpr (MODE == ROW_PD) {
     // dual step of the primal-dual iteration: y <- clip(y + sigma c, +-lambda_j), c = (K ubar)_j
     const float th = p.fw.thr[j];
+    typename S::Pair nv[PV::V];
     static_for<G::R>([&](auto r) {
       float y0, y1;
       S::unpack(gv[r], y0, y1);
       float n0 = clip(fmaf(p.sigma, a[r].x, y0), th);
       float n1 = clip(fmaf(p.sigma, a[r].y, y1), th);
-      S::store_pair(gp + 2 * (t + r * G::T), S::round2(n0, n1));
+      nv[r % PV::V] = S::round2(n0, n1);
+      if constexpr (r % PV::V == PV::V - 1) PV::store(gp + 2 * PV::V * ((r / PV::V) * G::T + t), nv);
       if constexpr (STATS) {
         const float d0 = n0 - y0, d1 = n1 - y1;
         acc[SLOT_DY2] += d0 * d0 + d1 * d1;
