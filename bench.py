@@ -16,6 +16,7 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import math
 import hashlib
 import json
 import os
@@ -72,6 +73,20 @@ def profiled_breakdown(pkg, torch, fn):
     prof = pkg.shs_profile_end()
     return {k: {"launches": n, "total_ms": round(ms, 4), "avg_ms": round(ms / max(n, 1), 5)}
             for k, (n, ms) in prof.items()}
+
+
+def host_cpu() -> str:
+    """Model name and logical CPU count of the host the oracle ran on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}; {os.cpu_count()} logical CPUs visible"
 
 
 def read_traffic(kernel_hash: str):
@@ -585,6 +600,8 @@ def main():
     ap.add_argument("--iters", type=int, default=None, help="ADMM iterations per step (default: workload's)")
     ap.add_argument("--cpu-iters", type=int, default=1, help="oracle iterations timed for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-1core", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the oracle sample on one core (single-image workloads)")
     ap.add_argument("--no-f32", action="store_true", help="skip the plain FP32 path run beside the main one")
     ap.add_argument("--no-hist", action="store_true",
                     help="residual reductions on the last iteration only (default: every iteration)")
@@ -667,6 +684,10 @@ def main():
     # whole-iteration roofline: algorithmic bytes per iteration over the iteration time
     bytes_iter = 2.0 * store_bytes * eta * w.q * w.n * w.n + 12.0 * w.q * w.n * w.n
     iter_hbm_frac = bytes_iter * its / 1e9 / HBM_PEAK_GBS
+    # and against the ALU: (2 eta + 2) q real 2-D FFTs per iteration at the conventional
+    # 2.5 N^2 log2(N^2) flops each, without the wedge pruning the kernels apply
+    flops_iter = (2 * eta + 2) * w.q * 2.5 * w.n * w.n * math.log2(w.n * w.n)
+    iter_tf = flops_iter * its / 1e12
 
     st = main_run["stats"]
     out = {
@@ -688,6 +709,11 @@ def main():
         "mpixel_label_filter_per_s": round(mplf, 1),
         "ms_per_iter": round(sec / args.steps / iters * 1e3, 4),
         "iteration_hbm_frac": round(iter_hbm_frac, 4),
+        "iteration_valu": {"algorithmic_flops": flops_iter, "TFLOPs": round(iter_tf, 2),
+                           "frac_of_157_3": round(iter_tf / FP32_VALU_PEAK_TFS, 4),
+                           "frac_of_nonpacked_78_6": round(iter_tf / (FP32_VALU_PEAK_TFS / 2), 4),
+                           "count": "(2 eta + 2) q real 2-D FFTs per iteration, 2.5 N^2 log2(N^2) flops each, "
+                                    "unpruned"},
         "roofline": roofline,
         "row_solve_hbm": row_solve_hbm,
         "kernel_breakdown_ms": breakdown,
@@ -742,7 +768,16 @@ def main():
             "sample": (f"{args.cpu_iters} ADMM iterations of the same workload from the zero state, FP64 "
                        f"numpy/scipy oracle ({workers} scipy.fft workers, numpy elementwise ops on one "
                        f"thread); {cdt:.1f} s"),
+            "host": host_cpu(),
         }
+        if args.cpu_1core and cdt < 10.0:      # bounded: skipped where the sample is long (C4)
+            oracle.transform.WORKERS = 1
+            log("cpu baseline: the same sample on one core")
+            t0 = time.perf_counter()
+            oracle.admm(s64, B, lam_f, w.gamma, args.cpu_iters)
+            c1 = time.perf_counter() - t0
+            out["cpu_baseline"]["value_1core"] = round(args.cpu_iters / c1, 6)
+            out["cpu_baseline"]["sample"] += f"; one core: {c1:.1f} s"
     print(json.dumps(out), flush=True)
 
 
