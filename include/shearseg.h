@@ -118,11 +118,12 @@ size_t shs_state_bytes(const shs_plan* plan);
 
 /* The plan's launch schedule as text (stable for the plan's life; "" for a null plan).
  * Mixed-radix plans (N not a power of two) choose it at creation by timing candidates on
- * their own kernels: rows per wave of the row pass, the stage order of the row and column
- * FFTs, and the filters per synthesis work item; the choice is cached per (GPU arch, N, J,
- * q, store) for the process and, if the environment variable SHEARSEG_TUNE_CACHE names a
- * file, there too (SHEARSEG_TUNE=0 keeps the default schedule).  The stage order changes
- * the FFT's rounding, so results are reproducible for a given schedule. */
+ * their own kernels: rows per wave and waves per block of the row pass, the stage order of
+ * the row and column FFTs, and the filters per synthesis work item; the choice is cached per
+ * (GPU arch, N, J, q, store) for the process and, if the environment variable
+ * SHEARSEG_TUNE_CACHE names a file, there too (SHEARSEG_TUNE=0 keeps the default schedule).
+ * The stage order changes the FFT's rounding, so results are reproducible for a given
+ * schedule. */
 const char* shs_plan_describe(const shs_plan* plan);
 
 /* eta = 1 + 4 (2^J - 1) (Theorem 2.2's system); -1 for J < 1. */

@@ -160,6 +160,7 @@ struct GenParams {
   FftPlan prow;   // length N/2
   FftPlan pcol;   // length N
   int n;
+  int wpb;        // waves per row-pass block (1, 2 or 4; the block is 64 wpb threads)
 };
 // Twiddle table of a mixed-radix plan, one device array: [0, N) exp(-2 pi i m / N), then
 // the stage table of the row FFT (N/2 entries), then that of the column FFT (N entries).
@@ -181,7 +182,9 @@ __device__ __forceinline__ void load_table(float2* dst, const float2* __restrict
 // Same modes and data contract as k_row.  Each wave transforms RW rows at once, stored
 // interleaved in LDS (bin k of row c at k * RW + c, two half-length complex buffers per
 // wave, dynamic shared memory), so that a stage's butterflies of all RW rows share the
-// wave's lanes; memory phases walk one row at a time (coalesced along the row).
+// wave's lanes; memory phases walk one row at a time (coalesced along the row).  A block
+// holds gp.wpb waves: more rows per wave fill the lanes in stages with few butterflies
+// (a large radix), fewer waves per block keep such blocks within their LDS share.
 __device__ __forceinline__ int tix_g(int ip, int row, int n) {
   return (ip >> 2) * (n * kGW) + row * kGW + (ip & (kGW - 1));     // floor for negative ip
 }
@@ -194,7 +197,7 @@ __device__ __forceinline__ void row_g_body(const RowParams& p, const GenParams& 
   __shared__ double red[4 * 4];
   const int n = gp.n, M = n / 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int row0 = (bid.x * 4 + wave) * RW;
+  const int row0 = (bid.x * gp.wpb + wave) * RW;
   const int ch = bid.y;
   const int j = ch % p.eta;
   float2* ltw = gsm;                 // exp(-2 pi i k / N), k <= M
@@ -326,7 +329,7 @@ __device__ __forceinline__ void row_g_body(const RowParams& p, const GenParams& 
   if constexpr (STATS) {
     double dd[4] = {double(acc[0]), double(acc[1]), double(acc[2]), double(acc[3])};
     dd[SLOT_L1] *= double(p.fw.lam[j]);
-    block_sum4<4>(dd, red);
+    block_sum4_n(dd, red, gp.wpb);
     if (threadIdx.x == 0) {
       double* o = p.partials + ((long long)bid.y * bid.gx + bid.x) * 4;
       o[0] = dd[0]; o[1] = dd[1]; o[2] = dd[2]; o[3] = dd[3];

@@ -157,6 +157,25 @@ __device__ __forceinline__ void block_sum4(double (&v)[4], double* sh) {
     }
   }
 }
+// The same over a block of `nwaves` waves (a launch-time block size).
+__device__ __forceinline__ void block_sum4_n(double (&v)[4], double* sh, int nwaves) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = wave_sum(v[i]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sh[wave * 4 + i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < nwaves; ++w) s += sh[w * 4 + i];
+      v[i] = s;
+    }
+  }
+}
 // Partial-sum slots: 0 = |dy|^2, 1 = |db|^2, 2 = <w, s>, 3 = sum lambda |v| (or energy l1).
 enum { SLOT_DY2 = 0, SLOT_DB2 = 1, SLOT_WS = 2, SLOT_L1 = 3 };
 

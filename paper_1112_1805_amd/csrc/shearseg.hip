@@ -28,6 +28,7 @@ struct shs_plan {
   int generic;         // 1: mixed-radix path (N not a power of two)
   int rpb;             // rows per row-pass block
   int rw;              // generic path: rows per wave of the row pass (1, 2 or 4)
+  int wpb;             // generic path: waves per row-pass block (1, 2 or 4)
   FftPlan prow, pcol;  // mixed-radix stage lists (generic path)
   float* psi;          // [eta][N][PP] dense filter bank (half spectrum)
   float2* tw;          // [N] exp(-2 pi i m / N), then (power-of-two N) the FFT stage tables
@@ -366,29 +367,37 @@ struct Pipe {
 };
 enum { COL_FWD = 0, COL_SYN = 1, COL_ANA = 2, COL_FINAL = 3 };
 
+// Dynamic LDS of a generic row-pass block: two half-length buffers of rw rows per wave,
+// then the twiddle tables.
+size_t row_g_lds_bytes(int M, int rw, int wpb, int n) {
+  return (size_t(wpb) * 2 * M * rw + row_tab_len(n)) * sizeof(float2);
+}
+constexpr size_t kRowGLdsMax = 64 * 1024;   // dynamic LDS a generic row block may take
+
 // Mixed-radix (generic) launchers: runtime N, one row per wave, LDS-resident transforms.
 struct GenPipe {
-  static GenParams gp(const shs_plan* p) { return GenParams{p->prow, p->pcol, p->n}; }
+  static GenParams gp(const shs_plan* p) { return GenParams{p->prow, p->pcol, p->n, p->wpb}; }
   template <int MODE, int ST, bool STATS>
   static void row_t(const shs_plan* p, const RowParams& rp, int channels, hipStream_t s) {
-    // 4 waves per block, p->rw rows per wave
+    // p->wpb waves per block, p->rw rows per wave
     const dim3 grid(p->n / p->rpb, channels);
-    const size_t lds = (size_t(4) * 2 * p->M * p->rw + row_tab_len(p->n)) * sizeof(float2);
+    const int threads = 64 * p->wpb;
+    const size_t lds = row_g_lds_bytes(p->M, p->rw, p->wpb, p->n);
     if (g_rec) {
       LaunchRec* r = nullptr;
       switch (p->rw) {
-        case 4: r = &rec_add(RK_ROW, &kg_row_g<MODE, ST, STATS, 4>, 256, p->n / p->rpb, channels, lds); break;
-        case 2: r = &rec_add(RK_ROW, &kg_row_g<MODE, ST, STATS, 2>, 256, p->n / p->rpb, channels, lds); break;
-        default: r = &rec_add(RK_ROW, &kg_row_g<MODE, ST, STATS, 1>, 256, p->n / p->rpb, channels, lds); break;
+        case 4: r = &rec_add(RK_ROW, &kg_row_g<MODE, ST, STATS, 4>, threads, p->n / p->rpb, channels, lds); break;
+        case 2: r = &rec_add(RK_ROW, &kg_row_g<MODE, ST, STATS, 2>, threads, p->n / p->rpb, channels, lds); break;
+        default: r = &rec_add(RK_ROW, &kg_row_g<MODE, ST, STATS, 1>, threads, p->n / p->rpb, channels, lds); break;
       }
       r->rp = rp;
       r->gp = gp(p);
       return;
     }
     switch (p->rw) {
-      case 4: hipLaunchKernelGGL((k_row_g<MODE, ST, STATS, 4>), grid, dim3(256), lds, s, rp, gp(p)); break;
-      case 2: hipLaunchKernelGGL((k_row_g<MODE, ST, STATS, 2>), grid, dim3(256), lds, s, rp, gp(p)); break;
-      default: hipLaunchKernelGGL((k_row_g<MODE, ST, STATS, 1>), grid, dim3(256), lds, s, rp, gp(p)); break;
+      case 4: hipLaunchKernelGGL((k_row_g<MODE, ST, STATS, 4>), grid, dim3(threads), lds, s, rp, gp(p)); break;
+      case 2: hipLaunchKernelGGL((k_row_g<MODE, ST, STATS, 2>), grid, dim3(threads), lds, s, rp, gp(p)); break;
+      default: hipLaunchKernelGGL((k_row_g<MODE, ST, STATS, 1>), grid, dim3(threads), lds, s, rp, gp(p)); break;
     }
   }
   static void row(const shs_plan* p, int mode, int store, bool stats, const RowParams& rp, int channels,
@@ -1183,7 +1192,7 @@ int batch_class(const shs_plan* p) {
   if (!p->generic) return p->n;
   const int lds3 = (3 * p->n * kGW + col_tab_len(p->n)) * int(sizeof(float2));
   const int bpc = std::min(4, (160 * 1024) / lds3);
-  return 100000 + p->rw * 10 + bpc;
+  return 100000 + p->wpb * 100 + p->rw * 10 + bpc;
 }
 
 void launch_batch_iter(const BatchIter& iter, char* dbase, hipStream_t s) {
@@ -1206,15 +1215,16 @@ void launch_batch_iter(const BatchIter& iter, char* dbase, hipStream_t s) {
 
 // ---------------------------------------------------------------- schedule tuning
 // Mixed-radix plans pick their launch schedule by timing candidates on their own kernels
-// at plan creation: rows per wave of the row pass, the stage order of the row FFT, the
-// stage order of the column FFT, and the filters per synthesis work item.  Rows per wave
-// and the synthesis item size leave every result bit-identical; the stage order changes the
-// FFT's rounding (results stay within the parity bounds, and are fixed for a given
-// schedule).  The choice is cached per (arch, N, J, q, store) for the process, and in the
+// at plan creation: rows per wave and waves per block of the row pass, the stage order of
+// the row FFT, the stage order of the column FFT, and the filters per synthesis work item.
+// The row-pass geometry and the synthesis item size leave the solution bit-identical (the
+// residual partial sums are grouped by block, so the histories can differ in the last
+// bits); the stage order changes the FFT's rounding (results stay within the parity
+// bounds, and are fixed for a given schedule).  The choice is cached per (arch, N, J, q, store) for the process, and in the
 // file named by SHEARSEG_TUNE_CACHE when set (one line per key); SHEARSEG_TUNE=0 keeps the
 // default schedule.
 struct TuneCfg {
-  int rw = 1, fc_syn = 1;
+  int rw = 1, wpb = 4, fc_syn = 1;
   std::vector<int> prow, pcol;
 };
 std::mutex g_tune_mu;
@@ -1246,10 +1256,11 @@ void tune_cache_load() {
   FILE* f = std::fopen(path, "r");
   if (!f) return;
   char key[128], prow[128], pcol[128];
-  int rw, fc;
-  while (std::fscanf(f, "%127s %d %d %127s %127s", key, &rw, &fc, prow, pcol) == 5) {
+  int rw, wpb, fc;
+  while (std::fscanf(f, "%127s %d %d %d %127s %127s", key, &rw, &wpb, &fc, prow, pcol) == 6) {
     TuneCfg c;
     c.rw = rw;
+    c.wpb = wpb;
     c.fc_syn = fc;
     c.prow = split_radices(prow);
     c.pcol = split_radices(pcol);
@@ -1262,7 +1273,7 @@ void tune_cache_store(const std::string& key, const TuneCfg& c) {
   const char* path = std::getenv("SHEARSEG_TUNE_CACHE");
   if (!path || !*path) return;
   if (FILE* f = std::fopen(path, "a")) {
-    std::fprintf(f, "%s %d %d %s %s\n", key.c_str(), c.rw, c.fc_syn, join_radices(c.prow, ',').c_str(),
+    std::fprintf(f, "%s %d %d %d %s %s\n", key.c_str(), c.rw, c.wpb, c.fc_syn, join_radices(c.prow, ',').c_str(),
                  join_radices(c.pcol, ',').c_str());
     std::fclose(f);
   }
@@ -1306,7 +1317,8 @@ shs_status apply_schedule(shs_plan* p, const TuneCfg& c, const StripLists& sl) {
   p->prow = pr;
   p->pcol = pc;
   p->rw = c.rw;
-  p->rpb = 4 * c.rw;
+  p->wpb = c.wpb;
+  p->rpb = c.wpb * c.rw;
   if (c.fc_syn != p->fc_syn) {
     std::vector<int4> isyn;
     build_items(sl.per_strip, sl.strip_off, c.fc_syn, false, isyn, nullptr, nullptr);
@@ -1331,6 +1343,7 @@ shs_status tune_schedule(shs_plan* p, const StripLists& sl) {
   tune_cache_load();
   TuneCfg base;
   base.rw = p->rw;
+  base.wpb = p->wpb;
   base.fc_syn = p->fc_syn;
   base.prow = fft_factors(p->M);
   base.pcol = fft_factors(p->n);
@@ -1338,15 +1351,17 @@ shs_status tune_schedule(shs_plan* p, const StripLists& sl) {
     if (e.first == key) {
       const shs_status st = apply_schedule(p, e.second, sl);
       if (st == SHS_OK)
-        std::snprintf(p->schedule, sizeof(p->schedule), "%s: rows/wave %d, row radices %s, column radices %s, "
-                      "synthesis run %d (cached)", key.c_str(), p->rw, join_radices(e.second.prow, 'x').c_str(),
+        std::snprintf(p->schedule, sizeof(p->schedule), "%s: rows/wave %d, waves/block %d, row radices %s, "
+                      "column radices %s, synthesis run %d (cached)", key.c_str(), p->rw, p->wpb,
+                      join_radices(e.second.prow, 'x').c_str(),
                       join_radices(e.second.pcol, 'x').c_str(), p->fc_syn);
       return st;
     }
   const char* off = std::getenv("SHEARSEG_TUNE");
   if (off && std::string(off) == "0") {
-    std::snprintf(p->schedule, sizeof(p->schedule), "%s: rows/wave %d, row radices %s, column radices %s, "
-                  "synthesis run %d (default)", key.c_str(), p->rw, join_radices(base.prow, 'x').c_str(),
+    std::snprintf(p->schedule, sizeof(p->schedule), "%s: rows/wave %d, waves/block %d, row radices %s, "
+                  "column radices %s, synthesis run %d (default)", key.c_str(), p->rw, p->wpb,
+                  join_radices(base.prow, 'x').c_str(),
                   join_radices(base.pcol, 'x').c_str(), p->fc_syn);
     return SHS_OK;
   }
@@ -1354,7 +1369,7 @@ shs_status tune_schedule(shs_plan* p, const StripLists& sl) {
   // a workspace for one label's channels, sized for the smallest rows per block
   const int rw0 = p->rw, rpb0 = p->rpb;
   p->rw = 1;
-  p->rpb = 4;
+  p->rpb = 1;
   const Layout L = make_layout(p);
   p->rw = rw0;
   p->rpb = rpb0;
@@ -1386,12 +1401,16 @@ shs_status tune_schedule(shs_plan* p, const StripLists& sl) {
   int tried = 0;
   // row pass: rows per wave x row stage order (one label's channels, state update on)
   float best_row = 1e30f;
-  for (int rw : {1, 2, 4}) {
-    if (rw == 4 && !(p->n % 16 == 0 && p->M <= 192)) continue;
-    if (rw == 2 && p->M > 384) continue;
+  for (int rw : {1, 2, 4})
+   for (int wpb : {4, 2, 1}) {
+    // a block's rows divide N and its LDS stays within the limit; one wave per block only
+    // where four rows per wave would not otherwise fit
+    if (p->n % (rw * wpb) != 0 || row_g_lds_bytes(p->M, rw, wpb, p->n) > kRowGLdsMax) continue;
+    if (wpb == 1 && rw < 4) continue;
     for (const auto& ord : order_candidates(base.prow)) {
       TuneCfg c = best;
       c.rw = rw;
+      c.wpb = wpb;
       c.prow = ord;
       shs_status st = apply_schedule(p, c, sl);
       if (st != SHS_OK) return st;
@@ -1406,9 +1425,9 @@ shs_status tune_schedule(shs_plan* p, const StripLists& sl) {
       rp.emit = 1;
       const float ms = time_ms([&] { run_row(cx, ROW_SOLVE, p->store, false, rp, p->eta); });
       ++tried;
-      if (ms < best_row) { best_row = ms; best.rw = rw; best.prow = ord; }
+      if (ms < best_row) { best_row = ms; best.rw = rw; best.wpb = wpb; best.prow = ord; }
     }
-  }
+   }
   // column passes: column stage order x synthesis run length (one label)
   float best_col = 1e30f;
   std::vector<int> fcs;
@@ -1444,8 +1463,9 @@ shs_status tune_schedule(shs_plan* p, const StripLists& sl) {
   if (st != SHS_OK) return st;
   tune_cache_store(key, best);
   const double tms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  std::snprintf(p->schedule, sizeof(p->schedule), "%s: rows/wave %d, row radices %s, column radices %s, synthesis "
-                "run %d (tuned: %d candidates, %.0f ms)", key.c_str(), p->rw, join_radices(best.prow, 'x').c_str(),
+  std::snprintf(p->schedule, sizeof(p->schedule), "%s: rows/wave %d, waves/block %d, row radices %s, column "
+                "radices %s, synthesis run %d (tuned: %d candidates, %.0f ms)", key.c_str(), p->rw, p->wpb,
+                join_radices(best.prow, 'x').c_str(),
                 join_radices(best.pcol, 'x').c_str(), p->fc_syn, tried, tms);
   return SHS_OK;
 }
@@ -1665,7 +1685,8 @@ shs_status shs_plan_create(const shs_shape* shape, int device, shs_plan** out) {
   // the two LDS buffers of a block (4 waves, 64 M rw bytes) stay at or below 48 KB, beside
   // the 8 N bytes of twiddle tables
   p->rw = pow2 ? 1 : (n % 16 == 0 && p->M <= 192) ? 4 : (p->M <= 384 ? 2 : 1);
-  p->rpb = pow2 ? by_size<RpbOf>(n) : 4 * p->rw;
+  p->wpb = 4;
+  p->rpb = pow2 ? by_size<RpbOf>(n) : p->wpb * p->rw;
   p->NS = p->M / p->W + 1;
   p->P = p->NS * p->W;  // columns of a dense spectrum plane (strip tiled); columns M+1.. unused
   p->PP = p->M + 16;    // row pitch of the dense filter bank
