@@ -25,8 +25,12 @@ Cases (the workload each one follows):
 * ``c2``    1024^2 RGB, q=5, J=4, 300 iterations (the precision-form workload);
 * ``c4q3``  2048^2 gray, J=4 (61 filters), the large-instance image class with q=3
             grey levels, 12 iterations (q=8 needs ~45 GB of FP64 state in the oracle).
+* ``c3``    nine images of the mixed-size batch workload at its full 200 iterations (FP32
+            state on the GPU), one per FFT size class: sides 96, 160, 224, 256, 352, 416, 544,
+            608 and 736 (largest prime factor of N/32: 3, 5, 7, 1, 11, 13, 17, 19, 23).  One
+            file, the keys of image i prefixed ``i<i>_``.
 
-Usage:  python tests/golden/make_admm_golden.py [c1 c2 c4q3]     (default: all)
+Usage:  python tests/golden/make_admm_golden.py [c1 c2 c4q3 c3]     (default: all)
 The oracle is run in chunks of iterations from the previous state (``init=``), which
 equals one continuous run (pinned in tests/test_oracle_admm.py); the histories of the
 chunks are concatenated.
@@ -44,7 +48,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import oracle as O  # noqa: E402
-from synth import make_c1, make_c2, make_c4  # noqa: E402
+from synth import make_c1, make_c2, make_c4, make_c3_image  # noqa: E402
 
 SAMPLE = 2048          # pixels whose w^K is stored (every label)
 SAMPLE_SEED = 4242
@@ -55,6 +59,7 @@ CASES = {
     "c2": lambda: (make_c2(), None),
     "c4q3": lambda: (make_c4(q=3), 12),
 }
+C3_IMAGES = (44, 24, 35, 17, 27, 2, 51, 0, 3)   # indices into the batch workload
 
 
 def path_of(case: str) -> str:
@@ -70,9 +75,8 @@ def sample_indices(n: int) -> np.ndarray:
     return np.sort(rng.choice(n * n, size=SAMPLE, replace=False)).astype(np.int64)
 
 
-def run_case(case: str) -> None:
-    w, iters = CASES[case]()
-    iters = w.iters if iters is None else iters
+def solve(case: str, w, iters: int) -> dict:
+    """The oracle's ADMM on workload w for `iters` iterations; the compact results."""
     t0 = time.time()
     s = O.datacost(f32(w.img), f32(w.codebook))
     bank = O.filter_bank(w.n, w.J)
@@ -91,24 +95,36 @@ def run_case(case: str) -> None:
     e = O.energy(res.w, s, bank, lam_f)
     idx = sample_indices(w.n)
     wf = res.w.reshape(w.q, -1)
-    out = dict(
-        case=np.array(case), n=np.int64(w.n), q=np.int64(w.q), J=np.int64(w.J), iters=np.int64(iters),
+    print(f"{case}: energy {e:.10g}, {time.time() - t0:.0f} s", flush=True)
+    return dict(
+        n=np.int64(w.n), q=np.int64(w.q), J=np.int64(w.J), iters=np.int64(iters),
         gamma=np.float64(w.gamma), lam=np.asarray(w.lam, dtype=np.float64),
         labels=res.labels.astype(np.int8), energy=np.float64(e),
         sample_idx=idx, w_sample=wf[:, idx].copy(), w_label_sums=wf.sum(axis=1),
         s_sum=np.float64(s.sum()), s_sq_sum=np.float64((s * s).sum()),
         **{k: np.concatenate(v) for k, v in hist.items()},
     )
+
+
+def run_case(case: str) -> None:
+    if case == "c3":
+        out = {"case": np.array(case), "images": np.array(C3_IMAGES, dtype=np.int64)}
+        for i in C3_IMAGES:
+            w = make_c3_image(i)
+            out.update({f"i{i}_{k}": v for k, v in solve(f"c3[{i}]", w, w.iters).items()})
+    else:
+        w, iters = CASES[case]()
+        out = dict(case=np.array(case), **solve(case, w, w.iters if iters is None else iters))
     np.savez_compressed(path_of(case), **out)
-    print(f"{case}: energy {e:.10g}, wrote {path_of(case)} ({os.path.getsize(path_of(case))} bytes), "
-          f"{time.time() - t0:.0f} s", flush=True)
+    print(f"{case}: wrote {path_of(case)} ({os.path.getsize(path_of(case))} bytes)", flush=True)
 
 
 def main(argv):
-    cases = argv or list(CASES)
+    known = list(CASES) + ["c3"]
+    cases = argv or known
     for c in cases:
-        if c not in CASES:
-            raise SystemExit(f"unknown case {c}; known: {list(CASES)}")
+        if c not in known:
+            raise SystemExit(f"unknown case {c}; known: {known}")
     for c in cases:
         run_case(c)
 
