@@ -91,8 +91,16 @@ inline int nl_build_graph(const NlGraphCfg& g, const float* img, int32_t* nbr, i
   const int rows_per_chunk = std::max(1, std::min(n, int((size_t(64) << 20) / (size_t(n) * K * sizeof(double)))));
   std::vector<double> dist(size_t(rows_per_chunk) * n * K);
   const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  std::vector<std::pair<double, int>> cand;
-  cand.reserve(K);
+  // Selection state: weights set per pixel, and per pixel a mask of the window offsets that
+  // land on its current neighbours (those candidates are excluded).  The k smallest
+  // (distance, index) pairs are kept in insertion order of that pair ordering.
+  std::vector<int> deg(n2, 0);
+  const int Wd = 2 * rr + 1, center = rr * Wd + rr;
+  auto kidx = [&](int o1, int o2) { const int e = (o1 + rr) * Wd + (o2 + rr); return e > center ? e - 1 : e; };
+  std::vector<uint64_t> excl((size_t(K) + 63) / 64);
+  std::vector<double> bd(size_t(std::max(m, 1)));
+  std::vector<int> bj(size_t(std::max(m, 1)));
+  std::vector<int> rowb(Wd, 0), colw(Wd, 0);   // wrapped row offsets / columns in the window
   for (int r0 = 0; r0 < n; r0 += rows_per_chunk) {
     const int r1 = std::min(n, r0 + rows_per_chunk);
     // distances of this chunk of rows in parallel (row-interleaved over threads)
@@ -101,29 +109,62 @@ inline int nl_build_graph(const NlGraphCfg& g, const float* img, int32_t* nbr, i
     const unsigned nt = std::min<unsigned>(hw, unsigned(rows));
     for (unsigned t = 0; t < nt; ++t)
       pool.emplace_back([&, t]() {
-        for (int r = r0 + int(t); r < r1; r += int(nt))
-          nl_distances_row(g, pad, ph, G, offs, r, dist.data() + size_t(r - r0) * n * K);
+        // a row's distances come out offset-major (vectorised along the row) and are stored
+        // pixel-major, so that the selection reads each pixel's K candidates contiguously
+        std::vector<double> tmp(size_t(n) * K);
+        for (int r = r0 + int(t); r < r1; r += int(nt)) {
+          nl_distances_row(g, pad, ph, G, offs, r, tmp.data());
+          double* out = dist.data() + size_t(r - r0) * n * K;
+          constexpr int B = 16;
+          for (int c0 = 0; c0 < n; c0 += B)
+            for (int k0 = 0; k0 < K; k0 += B)
+              for (int c = c0; c < std::min(n, c0 + B); ++c)
+                for (int kk = k0; kk < std::min(K, k0 + B); ++kk) out[size_t(c) * K + kk] = tmp[size_t(kk) * n + c];
+        }
       });
     for (auto& th : pool) th.join();
     // the sequential selection over the chunk's pixels
     for (int r = r0; r < r1; ++r) {
+      for (int o = -rr; o <= rr; ++o) rowb[size_t(o + rr)] = ((r + o) % n + n) % n * n;
       for (int c = 0; c < n; ++c) {
         const int i = r * n + c;
-        const int k = std::min(m, M2 - int(nb[i].size()));
+        const int k = std::min(m, M2 - deg[i]);
         if (k <= 0) continue;
-        cand.clear();
-        const double* d = dist.data() + size_t(r - r0) * n * K + c;
-        for (int kk = 0; kk < K; ++kk) {
-          const int j = ((r + offs[kk].x + n) % n) * n + ((c + offs[kk].y + n) % n);
-          if (j == i || int(nb[j].size()) >= M2) continue;
-          if (std::find(nb[i].begin(), nb[i].end(), j) != nb[i].end()) continue;
-          cand.emplace_back(d[size_t(kk) * n], j);
+        for (int o = -rr; o <= rr; ++o) colw[size_t(o + rr)] = ((c + o) % n + n) % n;
+        // offsets landing on a current neighbour x of i (every o = x - i mod n in the window)
+        std::fill(excl.begin(), excl.end(), uint64_t(0));
+        for (const int x : nb[i]) {
+          const int d1 = ((x / n - r) % n + n) % n, d2 = ((x % n - c) % n + n) % n;
+          for (int o1 = d1 - n * ((d1 + rr) / n); o1 <= rr; o1 += n)
+            for (int o2 = d2 - n * ((d2 + rr) / n); o2 <= rr; o2 += n)
+              if (o1 != 0 || o2 != 0) {
+                const int e = kidx(o1, o2);
+                excl[size_t(e) >> 6] |= uint64_t(1) << (e & 63);
+              }
         }
-        const int take = std::min<int>(k, int(cand.size()));
-        std::partial_sort(cand.begin(), cand.begin() + take, cand.end());
-        for (int t = 0; t < take; ++t) {
-          nb[i].push_back(cand[t].second);
-          nb[cand[t].second].push_back(i);
+        const double* d = dist.data() + (size_t(r - r0) * n + c) * K;
+        int nbest = 0;
+        for (int kk = 0; kk < K; ++kk) {
+          if ((excl[size_t(kk) >> 6] >> (kk & 63)) & 1) continue;
+          const int j = rowb[size_t(offs[kk].x + rr)] + colw[size_t(offs[kk].y + rr)];
+          if (j == i || deg[j] >= M2) continue;
+          const double dv = d[kk];
+          auto before = [&](int p) { return dv < bd[p] || (dv == bd[p] && j < bj[p]); };
+          if (nbest == k && !before(k - 1)) continue;
+          int pos = nbest < k ? nbest++ : k - 1;
+          while (pos > 0 && before(pos - 1)) {
+            bd[pos] = bd[pos - 1];
+            bj[pos] = bj[pos - 1];
+            --pos;
+          }
+          bd[pos] = dv;
+          bj[pos] = j;
+        }
+        for (int t = 0; t < nbest; ++t) {
+          nb[i].push_back(bj[t]);
+          nb[bj[t]].push_back(i);
+          ++deg[i];
+          ++deg[bj[t]];
         }
       }
     }
