@@ -103,6 +103,18 @@ def test_null_arguments():
     assert L.shs_solve_tv(None, None, None, None, 0, None, None, None, None, None) == pkg.SHS_E_INVALID
 
 
+def test_nl_graph_ties_match_oracle():
+    # four grey levels: many equal patch distances, so the tie rule (smaller linear index)
+    # decides most choices; a 48 x 48 image exercises the selection over many rows
+    import numpy as np
+    import oracle as O
+    rng = np.random.default_rng(5)
+    img = np.float32(np.floor(rng.uniform(size=(2, 48, 48)) * 4) / 4)
+    nbr, rev, md = pkg.nl_graph(img, 5, 15, 2.0, 5)
+    ref = O.nl_graph(img.astype(np.float64), 5, 15, 2.0, 5)
+    assert np.array_equal(nbr, ref.astype(np.int32))
+
+
 @pytest.mark.parametrize("n,C,m,window,seed", [(16, 1, 5, 15, 3), (20, 3, 5, 15, 4), (24, 1, 3, 9, 5), (16, 2, 8, 15, 6)])
 def test_nl_graph_matches_oracle(n, C, m, window, seed):
     # host-side graph builder of the library (no device) against the oracle's construction
