@@ -106,20 +106,92 @@ template <int R, bool INV> struct RegDFT {
   __device__ __forceinline__ static void run(cpx (&a)[R]);
 };
 
+// ---------------------------------------------------------------- twiddled butterflies
+// A butterfly (p, q) -> (p + q w, p - q w) costs four FMAs for the sum (the product folded
+// into the additions) and two for the difference, taken as 2 p - (p + q w): six
+// instructions instead of the eight of a complex product followed by two complex
+// additions (the FMA formulation of Linzer and Feig, IBM J. Res. Dev. 37(5), 1993).
+// INV multiplies by conj(w).
+template <bool INV>
+__device__ __forceinline__ cpx mul_tw(cpx q, cpx w) { return INV ? cmulc(q, w) : cmul(q, w); }
+template <bool INV>
+__device__ __forceinline__ cpx fmac_tw(cpx p, cpx q, cpx w) {   // p + q w
+  if constexpr (INV) return cpx{fmaf(q.x, w.x, fmaf(q.y, w.y, p.x)), fmaf(q.y, w.x, fmaf(-q.x, w.y, p.y))};
+  else return cpx{fmaf(q.x, w.x, fmaf(-q.y, w.y, p.x)), fmaf(q.y, w.x, fmaf(q.x, w.y, p.y))};
+}
+__device__ __forceinline__ cpx twice_minus(cpx p, cpx s) {      // 2 p - s
+  return cpx{fmaf(2.f, p.x, -s.x), fmaf(2.f, p.y, -s.y)};
+}
+template <bool INV>
+__device__ __forceinline__ void bfly_tw(cpx& p, cpx& q, cpx w) {
+  const cpx s = fmac_tw<INV>(p, q, w);
+  q = twice_minus(p, s);
+  p = s;
+}
+// The same with the compile-time twiddle W_NN^E; the multiples of a quarter turn need no
+// product and keep the plain additions.
+template <int E, int NN>
+constexpr bool quarter_turn() {
+  constexpr int e = ((E % NN) + NN) % NN;
+  return e == 0 || 4 * e == NN || 2 * e == NN || 4 * e == 3 * NN;
+}
+template <int E, int NN, bool INV>
+__device__ __forceinline__ void bfly_twc(cpx& p, cpx& q) {
+  if constexpr (quarter_turn<E, NN>()) {
+    const cpx u = twc<E, NN, INV>(q);
+    q = p - u;
+    p = p + u;
+  } else {
+    constexpr int e = ((E % NN) + NN) % NN;
+    constexpr float c = float(cos2pi(e, NN));
+    constexpr float sn = float(INV ? sin2pi(e, NN) : -sin2pi(e, NN));
+    const cpx s = cpx{fmaf(q.x, c, fmaf(-q.y, sn, p.x)), fmaf(q.x, sn, fmaf(q.y, c, p.y))};
+    q = twice_minus(p, s);
+    p = s;
+  }
+}
+
+// 4-point DFT (natural order) of x[j] * W_NN^{j K}: compile-time twiddles.
+template <int NN, int K, bool INV>
+__device__ __forceinline__ void dft4_twc(cpx (&z)[4]) {
+  bfly_twc<2 * K, NN, INV>(z[0], z[2]);                 // s0, d0
+  z[1] = twc<K, NN, INV>(z[1]);
+  bfly_twc<3 * K, NN, INV>(z[1], z[3]);                 // s1, d1 before the quarter turn
+  const cpx d1 = INV ? mul_i(z[3]) : mul_mi(z[3]);
+  const cpx s0 = z[0], d0 = z[2], s1 = z[1];
+  z[0] = s0 + s1;
+  z[2] = s0 - s1;
+  z[1] = d0 + d1;
+  z[3] = d0 - d1;
+}
+
+// A-point DFT of z[j] * W_NN^{j K} (folded butterflies for A = 2 and 4).
+template <int A, int NN, int K, bool INV>
+__device__ __forceinline__ void dft_twc(cpx (&z)[A]) {
+  if constexpr (A == 2) {
+    bfly_twc<K, NN, INV>(z[0], z[1]);
+  } else if constexpr (A == 4) {
+    dft4_twc<NN, K, INV>(z);
+  } else {
+    static_for<A>([&](auto j) { z[j] = twc<int(j) * K, NN, INV>(z[j]); });
+    RegDFT<A, INV>::run(z);
+  }
+}
+
 // R = A * B split in registers (four-step): B-point DFTs over the A interleaved
-// subsequences x[j + A m], twiddle W_R^{j k2}, then A-point DFTs across.
+// subsequences x[j + A m], then A-point DFTs across j of the outputs twiddled by W_R^{j k2}
+// (the twiddles folded into the butterflies).
 template <int R, int A, int B, bool INV>
 __device__ __forceinline__ void reg_dft_split(cpx (&a)[R]) {
   cpx y[A][B];
   static_for<A>([&](auto j) {
     static_for<B>([&](auto m) { y[j][m] = a[j + A * m]; });
     RegDFT<B, INV>::run(y[j]);
-    static_for<B>([&](auto k2) { y[j][k2] = twc<int(j) * int(k2), R, INV>(y[j][k2]); });
   });
   static_for<B>([&](auto k2) {
     cpx z[A];
     static_for<A>([&](auto j) { z[j] = y[j][k2]; });
-    RegDFT<A, INV>::run(z);
+    dft_twc<A, R, int(k2), INV>(z);
     static_for<A>([&](auto k1) { a[k2 + B * k1] = z[k1]; });
   });
 }
@@ -155,6 +227,46 @@ __device__ __forceinline__ void RegDFT<R, INV>::run(cpx (&a)[R]) {
   } else {
     static_assert(R == 32, "register DFT sizes 1..32");
     reg_dft_split<32, 4, 8, INV>(a);
+  }
+}
+
+// R-point DFT (natural order) of a[0] and a[r] * w[r], r >= 1 (INV: conj(w[r])), with the
+// runtime twiddles folded into the first butterfly layer.  TW0: a[0] is twiddled by w[0]
+// as well.  Same split as RegDFT.
+template <int R, bool INV, bool TW0 = false>
+__device__ __forceinline__ void dft_tw(cpx (&a)[R], const cpx (&w)[R]) {
+  if constexpr (R == 2) {
+    if constexpr (TW0) a[0] = mul_tw<INV>(a[0], w[0]);
+    bfly_tw<INV>(a[0], a[1], w[1]);
+  } else if constexpr (R == 4) {
+    if constexpr (TW0) a[0] = mul_tw<INV>(a[0], w[0]);
+    bfly_tw<INV>(a[0], a[2], w[2]);                     // s0, d0
+    a[1] = mul_tw<INV>(a[1], w[1]);
+    bfly_tw<INV>(a[1], a[3], w[3]);                     // s1, d1 before the quarter turn
+    const cpx d1 = INV ? mul_i(a[3]) : mul_mi(a[3]);
+    const cpx s0 = a[0], d0 = a[2], s1 = a[1];
+    a[0] = s0 + s1;
+    a[2] = s0 - s1;
+    a[1] = d0 + d1;
+    a[3] = d0 - d1;
+  } else {
+    static_assert(R == 8 || R == 16 || R == 32, "twiddled register DFT sizes 2, 4, 8, 16, 32");
+    constexpr int A = R == 8 ? 2 : 4, B = R / A;
+    cpx y[A][B];
+    static_for<A>([&](auto j) {
+      cpx wj[B];
+      static_for<B>([&](auto m) {
+        y[j][m] = a[j + A * m];
+        wj[m] = w[j + A * m];
+      });
+      dft_tw<B, INV, TW0 || (int(j) > 0)>(y[j], wj);
+    });
+    static_for<B>([&](auto k2) {
+      cpx z[A];
+      static_for<A>([&](auto j) { z[j] = y[j][k2]; });
+      dft_twc<A, R, int(k2), INV>(z);
+      static_for<A>([&](auto k1) { a[k2 + B * k1] = z[k1]; });
+    });
   }
 }
 
@@ -214,6 +326,7 @@ constexpr int col_lds_points() { return L + L / R; }
 // products cost a few FMAs each.
 template <int Q>
 __device__ __forceinline__ void pow2_twiddles(const float2* __restrict__ p, int stride, cpx (&w)[Q]) {
+  w[0] = cpx{1.f, 0.f};
   static_for<Q>([&](auto r) {
     if constexpr (r > 0 && (r & (r - 1)) == 0) w[r] = ld(p + (r - 1) * stride);
   });
@@ -229,6 +342,7 @@ __device__ __forceinline__ void pow2_twiddles(const float2* __restrict__ p, int 
 // sits in LDS, where a read costs no vector-memory bandwidth and no products are needed.
 template <int Q>
 __device__ __forceinline__ void all_twiddles(const float2* p, int stride, cpx (&w)[Q]) {
+  w[0] = cpx{1.f, 0.f};
   static_for<Q>([&](auto r) {
     if constexpr (r > 0) w[r] = ld(p + (r - 1) * stride);
   });
@@ -274,12 +388,8 @@ __device__ __forceinline__ void fft_run(cpx (&a)[R], const Addr& lds, int t, con
     else pow2_twiddles<RM>(sw + (R - 1) * T + tr, R, w);
     static_for<U>([&](auto u) {
       cpx c[RM];
-      static_for<RM>([&](auto r) {
-        cpx v = b[u * RM + r];
-        if constexpr (r > 0) v = INV ? cmulc(v, w[r]) : cmul(v, w[r]);
-        c[r] = v;
-      });
-      RegDFT<RM, INV>::run(c);
+      static_for<RM>([&](auto r) { c[r] = b[u * RM + r]; });
+      dft_tw<RM, INV>(c, w);
       // outputs (bf / R) * R * RM + k + r * R = ((tq + u*RM) * RM + r) * R + tr
       static_for<RM>([&](auto r) { st(lds.template at<R>((tq + u * RM) * RM + r, tr), c[r]); });
     });
@@ -289,15 +399,8 @@ __device__ __forceinline__ void fft_run(cpx (&a)[R], const Addr& lds, int t, con
   cpx wl[R];
   if constexpr (TWL) all_twiddles<R>(sw + t, T, wl);
   else pow2_twiddles<R>(sw + t, T, wl);
-  static_for<R>([&](auto r) {
-    cpx v = ld(lds.template at<R>(tq + r * RM, tr));
-    if constexpr (r > 0) {
-      const cpx w = wl[r];
-      v = INV ? cmulc(v, w) : cmul(v, w);
-    }
-    a[r] = v;
-  });
-  RegDFT<R, INV>::run(a);
+  static_for<R>([&](auto r) { a[r] = ld(lds.template at<R>(tq + r * RM, tr)); });
+  dft_tw<R, INV>(a, wl);
 }
 
 }  // namespace shs

@@ -481,24 +481,35 @@ __device__ __forceinline__ void row_c2r(cpx (&a)[RowGeom<N>::R], const float2* _
   // branching was measured slower: this pass keeps the vector-memory data path near
   // saturation.)
   cpx xp[G::R], xm[G::R];
+  const auto in_p = [&](int k0) { return k0 < cb + pitch && k0 + G::T > cb; };
+  const auto in_m = [&](int k0) { return k0 <= G::M - cb && k0 + G::T > G::M - cb - pitch; };
   static_for<G::R>([&](auto r) {
     constexpr int k0 = r * G::T;
     xp[r] = cpx{0.f, 0.f};
     xm[r] = cpx{0.f, 0.f};
-    if (k0 < cb + pitch && k0 + G::T > cb) xp[r] = B.load(row_bin<N, 1>(ip0, op0, r, row));
-    if (k0 <= G::M - cb && k0 + G::T > G::M - cb - pitch) xm[r] = B.load(row_bin<N, -1>(im0, om0, r, row));
+    if (in_p(k0)) xp[r] = B.load(row_bin<N, 1>(ip0, op0, r, row));
+    if (in_m(k0)) xm[r] = B.load(row_bin<N, -1>(im0, om0, r, row));
   });
+  // z[k] = s + i d W_N^{-k} with s = X[k] + conj(X[M-k]), d = X[k] - conj(X[M-k]): the
+  // product folded into FMAs; chunks with neither bin range in the window are zero.
   static_for<G::R>([&](auto r) {
-    const cpx s = xp[r] + conj(xm[r]), d = xp[r] - conj(xm[r]);
-    const cpx w = conj(pre_twiddle<N, r>(twl, t));   // W_N^{-k}
-    a[r] = s + mul_i(cmul(d, w));
+    constexpr int k0 = r * G::T;
+    if (in_p(k0) || in_m(k0)) {
+      const cpx s = xp[r] + conj(xm[r]), d = xp[r] - conj(xm[r]);
+      const cpx w = pre_twiddle<N, r>(twl, t);   // W_N^{k}
+      a[r] = cpx{fmaf(d.x, w.y, fmaf(-d.y, w.x, s.x)), fmaf(d.x, w.x, fmaf(d.y, w.y, s.y))};
+    } else {
+      a[r] = cpx{0.f, 0.f};
+    }
   });
   fft_run<G::M, G::R, G::RM, true, SYNC_WAVE, Addr, true>(a, A, t, twl + G::TW_PRE);
 }
 
 // Forward real FFT of a row held as pairs a[r] = (x[2p], x[2p+1]); writes the bins of
-// X[0..M] that fall in [cb, cb + pitch).
-template <int N, class Addr>
+// X[0..M] that fall in [cb, cb + pitch).  HALF: the row was passed in halved, which takes
+// the post-processing's factor 1/2 (exact: a power of two commutes with the FFT's
+// rounding).
+template <int N, bool HALF, class Addr>
 __device__ __forceinline__ void row_r2c(cpx (&a)[RowGeom<N>::R], float2* __restrict__ X, int row, int cb, int pitch,
                                         const Addr& A, int t, const float2* twl) {
   using G = RowGeom<N>;
@@ -517,10 +528,13 @@ __device__ __forceinline__ void row_r2c(cpx (&a)[RowGeom<N>::R], float2* __restr
       const cpx ym = conj(ld(A(unsigned(G::M - k) & unsigned(G::M - 1))));
       const cpx s = yk + ym, d = yk - ym;
       const cpx w = pre_twiddle<N, r>(twl, t);   // W_N^{k}
-      B.store(row_bin<N, 1>(ip0, op0, r, row), (s - mul_i(cmul(d, w))) * 0.5f);
+      // (s - i d w) / 2, the product folded into FMAs
+      cpx x = cpx{fmaf(d.x, w.y, fmaf(d.y, w.x, s.x)), fmaf(-d.x, w.x, fmaf(d.y, w.y, s.y))};
+      if constexpr (!HALF) x = x * 0.5f;
+      B.store(row_bin<N, 1>(ip0, op0, r, row), x);
     }
   });
-  if (t == 0) B.store(tix<N>(G::M - cb, row), cpx{a[0].x - a[0].y, 0.f});
+  if (t == 0) B.store(tix<N>(G::M - cb, row), cpx{HALF ? 2.f * (a[0].x - a[0].y) : a[0].x - a[0].y, 0.f});
 }
 
 template <int N, int MODE, int ST, bool STATS>
@@ -614,8 +628,8 @@ __device__ __forceinline__ void row_body(const RowParams& p, BlockId bid) {
         acc[SLOT_L1] += fabsf(n0 - nb0);
         acc[SLOT_L1] += fabsf(n1 - nb1);
       }
-      // next adjoint input v - b_v = g - 2 clip(g)
-      a[r] = cpx{n0 - 2.f * nb0, n1 - 2.f * nb1};
+      // next adjoint input v - b_v = g - 2 clip(g), passed on halved (see row_r2c)
+      a[r] = cpx{fmaf(0.5f, n0, -nb0), fmaf(0.5f, n1, -nb1)};
     });
     // Complete the residual partial sums here (an empty asm that reads and writes them):
     // otherwise the compiler sinks them past the forward FFT and keeps every per-pixel
@@ -658,7 +672,7 @@ __device__ __forceinline__ void row_body(const RowParams& p, BlockId bid) {
       const int f = ch % p.lout.nf;
       plane_geom(p.lout, f, cb, pitch, off);
       float2* X = p.spec_out + (ch / p.lout.nf) * p.lout.ls + off;
-      row_r2c<N>(a, X, row, cb, pitch, A, t, twl);
+      row_r2c<N, MODE == ROW_SOLVE || MODE == ROW_PRIME>(a, X, row, cb, pitch, A, t, twl);
     }
   }
   if constexpr (STATS) {
