@@ -486,9 +486,29 @@ __device__ __forceinline__ void row_c2r(cpx (&a)[RowGeom<N>::R], const float2* _
   static_for<G::R>([&](auto r) {
     constexpr int k0 = r * G::T;
     xp[r] = cpx{0.f, 0.f};
-    xm[r] = cpx{0.f, 0.f};
     if (in_p(k0)) xp[r] = B.load(row_bin<N, 1>(ip0, op0, r, row));
-    if (in_m(k0)) xm[r] = B.load(row_bin<N, -1>(im0, om0, r, row));
+  });
+  // Each bin is loaded once.  The mirrored bins X[M - k] come from the lanes that loaded
+  // them, through the LDS crossbar (ds_bpermute) instead of the vector-memory path: for
+  // t > 0, bin M - t - r T = (T - t) + (R - 1 - r) T is lane T - t's xp[R - 1 - r] (zero
+  // where that chunk was not loaded: outside the window); lane t = 0 holds X[M - r T]
+  // itself as xp[R - r] and loads X[M].
+  const int src = (int(threadIdx.x & 63u) - t + ((G::T - t) & (G::T - 1))) << 2;
+  cpx xnyq = cpx{0.f, 0.f};
+  if (t == 0 && in_m(0)) xnyq = B.load(om0);
+  static_for<G::R>([&](auto r) {
+    constexpr int k0 = r * G::T;
+    constexpr int rs = G::R - 1 - r;
+    xm[r] = cpx{0.f, 0.f};
+    if (in_m(k0)) {
+      cpx v = cpx{__int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(xp[rs].x))),
+                  __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(xp[rs].y)))};
+      if (t == 0) {
+        if constexpr (r == 0) v = xnyq;
+        else v = xp[G::R - r];
+      }
+      xm[r] = v;
+    }
   });
   // z[k] = s + i d W_N^{-k} with s = X[k] + conj(X[M-k]), d = X[k] - conj(X[M-k]): the
   // product folded into FMAs; chunks with neither bin range in the window are zero.
