@@ -358,12 +358,52 @@ __device__ __forceinline__ void all_twiddles(const float2* p, int stride, cpx (&
 template <int L, int R, int RM>
 constexpr int stage_tw_size() { return (R - 1) * (L / R) + (RM - 1) * R; }
 
+// The power-of-two rows of that table only (r = 1, 2, 4, ...), packed: last stage
+// cw[log2(r) T + t], then middle stage cw[log2(R) T + log2(r) R + tr].  The other powers
+// are products of two of them, as in pow2_twiddles.
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+template <int L, int R, int RM>
+constexpr int stage_tw_pow2_size() { return ilog2c(R) * (L / R) + ilog2c(RM) * R; }
+// Copies the packed power-of-two rows of the stage table `sw` (global) into `cw` (LDS);
+// threads tid = 0, nthr, 2 nthr, ... of the block share the copy.  The caller synchronises.
+template <int L, int R, int RM>
+__device__ __forceinline__ void load_stage_tw_pow2(float2* cw, const float2* __restrict__ sw, int tid, int nthr) {
+  constexpr int T = L / R, LAST = ilog2c(R) * T;
+  for (int e = tid; e < stage_tw_pow2_size<L, R, RM>(); e += nthr) {
+    int src;
+    if (e < LAST) {
+      src = ((1 << (e / T)) - 1) * T + e % T;
+    } else {
+      const int e2 = e - LAST;
+      src = (R - 1) * T + ((1 << (e2 / R)) - 1) * R + e2 % R;
+    }
+    cw[e] = sw[src];
+  }
+}
+// Q - 1 twiddles from the packed rows (entry log2(r) * stride for r = 1, 2, 4, ...; the
+// others products of two of them).
+template <int Q>
+__device__ __forceinline__ void pow2_twiddles_packed(const float2* p, int stride, cpx (&w)[Q]) {
+  w[0] = cpx{1.f, 0.f};
+  static_for<Q>([&](auto r) {
+    if constexpr (r > 0 && (r & (r - 1)) == 0) w[r] = ld(p + ilog2c(r) * stride);
+  });
+  static_for<Q>([&](auto r) {
+    if constexpr (r > 0 && (r & (r - 1)) != 0) {
+      constexpr int hi = 1 << (31 - __builtin_clz(unsigned(r)));
+      w[r] = cmul(w[hi], w[r - hi]);
+    }
+  });
+}
+
 // In-register/LDS Stockham FFT of length L.  On entry a[r] holds point t + r*T; on exit
 // a[r] holds output bin t + r*T.  `sw` is the stage twiddle table of (L, R, RM) above.
 // The caller must have synchronised any earlier reader of the LDS region before the call
-// (the routine synchronises before its first LDS write).  TWL: `sw` points to a copy of
-// the table in LDS, and every twiddle power is read from it.
-template <int L, int R, int RM, bool INV, int SK, class Addr, bool TWL = false>
+// (the routine synchronises before its first LDS write).  TWL = 0: `sw` is the table in
+// global memory (power-of-two powers loaded, the others formed by products); 1: `sw` points
+// to a copy of the table in LDS and every power is read from it; 2: `sw` points to the
+// packed power-of-two rows in LDS (load_stage_tw_pow2), the others formed by products.
+template <int L, int R, int RM, bool INV, int SK, class Addr, int TWL = 0>
 __device__ __forceinline__ void fft_run(cpx (&a)[R], const Addr& lds, int t, const float2* __restrict__ sw) {
   static_assert(R * R * RM == L && R % RM == 0, "FFT configuration");
   constexpr int T = L / R;                 // = R * RM
@@ -384,7 +424,8 @@ __device__ __forceinline__ void fft_run(cpx (&a)[R], const Addr& lds, int t, con
     });
     fft_sync<SK>();
     cpx w[RM];
-    if constexpr (TWL) all_twiddles<RM>(sw + (R - 1) * T + tr, R, w);
+    if constexpr (TWL == 1) all_twiddles<RM>(sw + (R - 1) * T + tr, R, w);
+    else if constexpr (TWL == 2) pow2_twiddles_packed<RM>(sw + ilog2c(R) * T + tr, R, w);
     else pow2_twiddles<RM>(sw + (R - 1) * T + tr, R, w);
     static_for<U>([&](auto u) {
       cpx c[RM];
@@ -397,7 +438,8 @@ __device__ __forceinline__ void fft_run(cpx (&a)[R], const Addr& lds, int t, con
   }
   // last stage: radix R, Ns = L/R, butterfly bf = t; input t + r*T = (tq + r*RM) * R + tr
   cpx wl[R];
-  if constexpr (TWL) all_twiddles<R>(sw + t, T, wl);
+  if constexpr (TWL == 1) all_twiddles<R>(sw + t, T, wl);
+  else if constexpr (TWL == 2) pow2_twiddles_packed<R>(sw + t, T, wl);
   else pow2_twiddles<R>(sw + t, T, wl);
   static_for<R>([&](auto r) { a[r] = ld(lds.template at<R>(tq + r * RM, tr)); });
   dft_tw<R, INV>(a, wl);

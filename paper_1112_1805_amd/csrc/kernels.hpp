@@ -522,7 +522,7 @@ __device__ __forceinline__ void row_c2r(cpx (&a)[RowGeom<N>::R], const float2* _
       a[r] = cpx{0.f, 0.f};
     }
   });
-  fft_run<G::M, G::R, G::RM, true, SYNC_WAVE, Addr, true>(a, A, t, twl + G::TW_PRE);
+  fft_run<G::M, G::R, G::RM, true, SYNC_WAVE, Addr, 1>(a, A, t, twl + G::TW_PRE);
 }
 
 // Forward real FFT of a row held as pairs a[r] = (x[2p], x[2p+1]); writes the bins of
@@ -533,7 +533,7 @@ template <int N, bool HALF, class Addr>
 __device__ __forceinline__ void row_r2c(cpx (&a)[RowGeom<N>::R], float2* __restrict__ X, int row, int cb, int pitch,
                                         const Addr& A, int t, const float2* twl) {
   using G = RowGeom<N>;
-  fft_run<G::M, G::R, G::RM, false, SYNC_WAVE, Addr, true>(a, A, t, twl + G::TW_PRE);
+  fft_run<G::M, G::R, G::RM, false, SYNC_WAVE, Addr, 1>(a, A, t, twl + G::TW_PRE);
   const int tq = int(unsigned(t) / G::R), tr = int(unsigned(t) % G::R);
   fft_sync<SYNC_WAVE>();
   static_for<G::R>([&](auto r) { st(A.template at<G::R>(tq + r * G::RM, tr), a[r]); });
@@ -812,6 +812,7 @@ __device__ __forceinline__ void col_syn_body(const ColParams& p, BlockId bid) {
   constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
   __shared__ float2 lds[col_lds_points<N, R>() * W];
   __shared__ ItemStage<W> stg;
+  __shared__ float2 ctw[stage_tw_pow2_size<N, R, G::RM>()];   // packed stage twiddles
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int4 it = p.items[bid.x];
   const int k1 = it.x * W + c;
@@ -819,6 +820,7 @@ __device__ __forceinline__ void col_syn_body(const ColParams& p, BlockId bid) {
   const int l = bid.y;
   const ColAddr<W, R> A{lds + c};
   stage_item<N>(p, it, stg);
+  load_stage_tw_pow2<N, R, G::RM>(ctw, p.tw + col_sw_off<N>(), threadIdx.x, G::THREADS);
   cpx uh[R];
   const float2* U = p.in + l * (long long)N * p.P + (long long)it.x * (N * W) + c;
   static_for<R>([&](auto r) { uh[r] = valid ? ld(U + (t + r * T) * W) : cpx{0.f, 0.f}; });
@@ -833,7 +835,7 @@ __device__ __forceinline__ void col_syn_body(const ColParams& p, BlockId bid) {
     if constexpr (G::PREFETCH) {
       if (i + 1 < it.z) PB.load<N, R, T>(stg.win[i + 1][c], t, ps);
     }
-    fft_run<N, R, G::RM, true, SYNC_BLOCK>(a, A, t, p.tw + col_sw_off<N>());
+    fft_run<N, R, G::RM, true, SYNC_BLOCK, ColAddr<W, R>, 2>(a, A, t, ctw);
     const int4 geo = stg.geo[i];
     float2* o = p.out + l * p.tl.ls + geo_off(geo) + (long long)(it.x - geo.x / W) * (N * W) + c;
     if (valid) {
@@ -870,6 +872,7 @@ __device__ __forceinline__ void col_ana_body(const ColParams& p, BlockId bid) {
   constexpr int R = G::R, T = G::T, W = G::W, M = N / 2;
   __shared__ float2 lds[col_lds_points<N, R>() * W];
   __shared__ ItemStage<W> stg;
+  __shared__ float2 ctw[stage_tw_pow2_size<N, R, G::RM>()];   // packed stage twiddles
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int4 it = p.items[bid.x];
   const int k1 = it.x * W + c;
@@ -877,6 +880,7 @@ __device__ __forceinline__ void col_ana_body(const ColParams& p, BlockId bid) {
   const int l = bid.y;
   const ColAddr<W, R> A{lds + c};
   stage_item<N>(p, it, stg);
+  load_stage_tw_pow2<N, R, G::RM>(ctw, p.tw + col_sw_off<N>(), threadIdx.x, G::THREADS);
   __syncthreads();
   // T2 column of item filter i; columns past N/2 are never written and read as zero
   auto load_col = [&](int i, cpx (&v)[R]) {
@@ -899,7 +903,7 @@ __device__ __forceinline__ void col_ana_body(const ColParams& p, BlockId bid) {
     }
     float ps[R];
     PB.load<N, R, T>(stg.win[i][c], t, ps);
-    fft_run<N, R, G::RM, false, SYNC_BLOCK>(a, A, t, p.tw + col_sw_off<N>());
+    fft_run<N, R, G::RM, false, SYNC_BLOCK, ColAddr<W, R>, 2>(a, A, t, ctw);
     static_for<R>([&](auto r) { acc[r] = acc[r] + a[r] * ps[r]; });
   }
   if (it.w < 0) {
